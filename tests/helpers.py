@@ -1,0 +1,54 @@
+"""Test helpers: turn a workload dict into an oracle problem (oracle-side
+parameter resolution) and compare moment fields."""
+import math
+
+import numpy as np
+
+from oracle import oracle as orc
+
+
+def xi_max(prob):
+    D = prob["dim"]
+    return math.sqrt(sum(max(abs(prob["vmin"][d]), abs(prob["vmax"][d])) ** 2 for d in range(D)))
+
+
+def oracle_dt(prob):
+    if prob.get("dt"):
+        return float(prob["dt"])
+    D = prob["dim"]
+    dx = min((prob["hi"][d] - prob["lo"][d]) / prob["n"][d] for d in range(D))
+    return orc.cfl_dt(prob.get("cfl", 0.5), dx, xi_max(prob))
+
+
+def oracle_problem(prob, dt=None):
+    q = dict(prob)
+    relax = prob.get("relax", "kn")
+    if relax == "kn":
+        L = prob.get("L_ref") or (prob["hi"][0] - prob["lo"][0])
+        rho_ref = prob.get("rho_ref") or float(np.mean(prob["rho"]))
+        q["mu_ref"] = orc.mu_ref_from_kn(prob["Kn"], L, rho_ref, prob.get("R", 0.5), prob.get("T_ref", 1.0))
+        q["relax"] = "mu"
+    elif relax == "mu":
+        q["relax"] = "mu"
+    else:
+        q["relax"] = "tau"
+    q["dt"] = dt if dt is not None else oracle_dt(prob)
+    return q
+
+
+def make_oracle(prob, dt=None):
+    o = orc.Oracle(oracle_problem(prob, dt))
+    o.init(prob["rho"], prob["u"], prob["T"])
+    return o
+
+
+def moment_errors(ref, got, gamma=5.0 / 3.0, R=0.5):
+    """Per-cell relative errors on rho and T; normwise error on u scaled by
+    max(max|u|, sound speed at T_ref = 1)."""
+    rho0, u0, T0 = ref
+    rho1, u1, T1 = got
+    e_rho = float(np.max(np.abs(rho1 - rho0) / np.abs(rho0)))
+    e_T = float(np.max(np.abs(T1 - T0) / np.abs(T0)))
+    scale = max(float(np.max(np.abs(u0))), math.sqrt(gamma * R * 1.0))
+    e_u = float(np.max(np.abs(u1 - u0))) / scale
+    return e_rho, e_u, e_T
