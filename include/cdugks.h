@@ -1,0 +1,191 @@
+/*
+ * cdugks.h -- C ABI of the MI355X (gfx950) CDUGKS time-step library.
+ *
+ * The library advances the reduced distributions g (mass) and b (total
+ * energy) of the Coupled Discrete Unified Gas Kinetic Scheme over the full
+ * phase-space grid (spatial cells x discrete velocities) of Zamora, Slaughter
+ * & Abel, "Computational Fluid Dynamics with the Coupled Discrete Unified Gas
+ * Kinetic Scheme" (arXiv 2208.09132), Sec. 2 and Sec. 2.1.  Every stage of a
+ * step runs in hand-written HIP kernels on one GPU.
+ *
+ * Conventions
+ *  - All functions return an int status (CDUGKS_OK = 0, negative on error);
+ *    no exception crosses the ABI.  cdugks_last_error() gives a thread-local
+ *    message for the last failure on the calling thread.
+ *  - Host arrays passed in are owned by the caller and only read during the
+ *    call (cdugks_submit copies them).  Device state is owned by the library,
+ *    or lives in a caller-supplied arena.
+ *  - Moment arrays are structure-of-arrays: rho[N], u[dim][N], T[N], cells
+ *    row-major with x fastest, N = n[0]*n[1]*n[2] over the used dimensions.
+ *  - Streams are hipStream_t passed as void* (NULL = default stream).
+ *  - An error raised while a step runs on the device (non-physical state:
+ *    rho <= 0, T <= 0 or non-finite, in a cell or at a face) is sticky on the
+ *    context and reported by cdugks_sync / cdugks_moments; the state after it
+ *    is unspecified.
+ */
+#ifndef CDUGKS_H
+#define CDUGKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CDUGKS_OK = 0,
+    CDUGKS_PENDING = 1,
+    CDUGKS_ERR_INVALID = -1,
+    CDUGKS_ERR_NOMEM = -2,
+    CDUGKS_ERR_DEVICE = -3,
+    CDUGKS_ERR_NONPHYSICAL = -4,
+    CDUGKS_ERR_TOO_LARGE = -5,
+    CDUGKS_ERR_BUSY = -6,
+    CDUGKS_ERR_UNKNOWN = -7
+};
+
+/* Boundary conditions per dimension (both sides).  Periodic wraps; outflow
+ * copies the boundary cell into the ghost layers (zero gradient).  The paper
+ * uses Dirichlet for Sod (Sec. 3.1) and periodic elsewhere (Sec. 3.4, Sec. 4). */
+enum { CDUGKS_BC_PERIODIC = 0, CDUGKS_BC_OUTFLOW = 1 };
+
+/* How the relaxation time is given (Sec. 2, eq. visc and tau_g = mu/p):
+ *  KN : Knudsen number; hard-sphere mean free path 16 mu/(5 rho sqrt(2 pi R T))
+ *       at (rho_ref, T_ref) over the length L_ref gives mu_ref, then
+ *       mu = mu_ref (T/T_ref)^omega.
+ *  MU : mu_ref given directly.
+ *  TAU: constant tau_g (may be +inf: free streaming). */
+enum { CDUGKS_RELAX_KN = 0, CDUGKS_RELAX_MU = 1, CDUGKS_RELAX_TAU = 2 };
+
+/* Velocity quadrature per axis (Sec. 2 conserved variables; Sec. 3.1):
+ * composite trapezoid, or composite fourth-order Newton-Cotes, which needs
+ * nv = 4k+1 nodes.  Nodes include both end points. */
+enum { CDUGKS_QUAD_TRAPEZOID = 0, CDUGKS_QUAD_BOOLE = 1 };
+
+/* Storage precision of g and b in device memory.  The conserved variables,
+ * equilibria, velocity sums and relaxation coefficients are FP64 in every
+ * mode; F32 only rounds the stored distributions. */
+enum { CDUGKS_STORE_F64 = 0, CDUGKS_STORE_F32 = 1 };
+
+typedef struct {
+    int dim;                /* D = 1, 2 or 3 */
+    int64_t n[3];           /* cells per dimension (entries >= dim ignored) */
+    double lo[3], hi[3];    /* domain box; uniform Cartesian cells */
+    int bc[3];              /* CDUGKS_BC_* per dimension */
+} cdugks_space;
+
+typedef struct {
+    int64_t nv[3];          /* discrete velocities per axis (>= 2) */
+    double vmin[3], vmax[3];/* velocity box per axis */
+    int quadrature;         /* CDUGKS_QUAD_* */
+} cdugks_velocity;
+
+typedef struct {
+    double gamma;           /* adiabatic index, 1 < gamma <= 5/3; K = (5-3 gamma)/(gamma-1) */
+    double Pr;              /* Prandtl number = tau_g / tau_b, > 0 */
+    double R;               /* gas constant (the paper uses 1/2) */
+    double omega;           /* viscosity exponent w of eq. visc */
+    int relax_mode;         /* CDUGKS_RELAX_* */
+    double Kn, L_ref, rho_ref, T_ref;  /* KN mode; L_ref <= 0 -> x extent,
+                                          rho_ref <= 0 -> mean initial density,
+                                          T_ref <= 0 -> 1 */
+    double mu_ref;          /* MU mode */
+    double tau;             /* TAU mode, may be +inf */
+    double cfl;             /* alpha of the static CFL step (Sec. 4) */
+    double dt;              /* <= 0: dt = cfl dx_min / (2 max_i |xi_i|) */
+    int storage;            /* CDUGKS_STORE_* */
+    int velocity_slices;    /* velocity-loop split across workgroups; 0 = auto */
+} cdugks_params;
+
+typedef struct cdugks_ctx cdugks_ctx;
+
+/* Device bytes cdugks_init needs for this problem (for arenas and budgets). */
+int cdugks_required_bytes(const cdugks_space* space, const cdugks_velocity* vel,
+                          const cdugks_params* params, size_t* bytes);
+
+/* Create a problem and set its state to the discrete equilibria of the given
+ * moments (Sec. 3.4: every problem starts from the Maxwellian of its moments).
+ * rho[N] > 0, u[dim][N], T[N] > 0 are host arrays.  hip_stream is the stream
+ * all work of this context is enqueued on.  arena (device pointer, >= the
+ * cdugks_required_bytes figure, 256-byte aligned) may be NULL, in which case
+ * the library allocates.  Validation failures return CDUGKS_ERR_INVALID:
+ * dim outside 1..3, n < 1, nv < 2, Boole with nv != 4k+1, gamma outside
+ * (1, 5/3], Pr <= 0, R <= 0, rho <= 0, T <= 0, a requested dt above the CFL
+ * bound.  Returns after enqueueing the initialisation. */
+int cdugks_init(const cdugks_space* space, const cdugks_velocity* vel,
+                const cdugks_params* params, const double* rho, const double* u,
+                const double* T, void* hip_stream, void* arena, size_t arena_bytes,
+                cdugks_ctx** out);
+
+/* Enqueue nsteps time steps (Sec. 2.1) on the context's stream; returns
+ * without waiting.  Steps are replayed from a captured HIP graph. */
+int cdugks_step(cdugks_ctx* ctx, int64_t nsteps);
+
+/* Wait for the context's stream; returns the sticky device error if any. */
+int cdugks_sync(cdugks_ctx* ctx);
+
+/* rho[N], u[dim][N], T[N] from the carried conserved variables (Sec. 2:
+ * u = (rho u)/rho, T = (gamma-1)/R (E - u^2/2)).  If device_ptrs != 0 the
+ * three pointers are device memory and the call only enqueues; otherwise
+ * they are host memory and the call waits. */
+int cdugks_moments(cdugks_ctx* ctx, double* rho, double* u, double* T, int device_ptrs);
+
+/* Conserved variables W[N][dim+2] = (rho, rho u, rho E) copied to host. */
+int cdugks_conserved(cdugks_ctx* ctx, double* W);
+
+/* Distributions g[V][N], b[V][N] (velocity-major, cells fastest, FP64) copied
+ * to host, V = nv[0]*nv[1]*nv[2] with the velocity index x fastest. */
+int cdugks_distributions(cdugks_ctx* ctx, double* g, double* b);
+
+/* Time step, simulated time and number of completed steps. */
+int cdugks_info(cdugks_ctx* ctx, double* dt, double* t, int64_t* steps);
+
+/* Timing helper: advance nsteps steps launching every phase on its own, with
+ * HIP events recorded between the phases on the context's stream; ms[4]
+ * receives the mean duration per step (milliseconds) of the four kernels of a
+ * step: face sums, face closure, cell closure, update.  Waits for the stream. */
+int cdugks_profile_phases(cdugks_ctx* ctx, int64_t nsteps, double* ms);
+
+/* Release the context (waits for its stream).  NULL-safe. */
+void cdugks_destroy(cdugks_ctx* ctx);
+
+/* ---------------- batched form -------------------------------------------
+ * Several independent problems advanced together: each kernel phase of a step
+ * is ONE launch over a device work list that covers every tile of every
+ * problem, and step sequences are captured as HIP graphs of chunk_steps
+ * steps.  Every problem keeps its own context (same stream required) and
+ * gets bitwise the same result as when stepped alone. */
+typedef struct cdugks_batch cdugks_batch;
+
+int cdugks_batch_create(cdugks_ctx* const* ctxs, int count, int chunk_steps,
+                        cdugks_batch** out);
+int cdugks_batch_step(cdugks_batch* batch, int64_t nsteps);
+void cdugks_batch_destroy(cdugks_batch* batch);
+
+/* ---------------- served form --------------------------------------------
+ * Continuous batching: requests are admitted while slots and the device
+ * memory budget allow, join the running batch at the next chunk boundary,
+ * and leave it when their step count is reached; a host thread drives the
+ * device.  Thread-safe. */
+typedef struct cdugks_server cdugks_server;
+
+int cdugks_server_create(size_t hbm_budget, int max_active, int chunk_steps,
+                         void* hip_stream, cdugks_server** out);
+/* Copies the request.  CDUGKS_ERR_TOO_LARGE if it can never fit the budget. */
+int cdugks_submit(cdugks_server* srv, const cdugks_space* space, const cdugks_velocity* vel,
+                  const cdugks_params* params, const double* rho, const double* u,
+                  const double* T, int64_t nsteps, uint64_t* ticket);
+/* CDUGKS_PENDING until done; then fills the moments (host arrays sized for
+ * the request) and the queueing and service times, and forgets the ticket. */
+int cdugks_poll(cdugks_server* srv, uint64_t ticket, double* rho, double* u, double* T,
+                double* t_queue_s, double* t_service_s);
+void cdugks_server_destroy(cdugks_server* srv);
+
+/* Thread-local message describing the last error on this thread. */
+const char* cdugks_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CDUGKS_H */

@@ -31,6 +31,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define GHOST 3
 
@@ -641,4 +644,13 @@ void oracle_set_state(oracle_state* s, const double* g, const double* b, const d
 }
 
 double oracle_time(const oracle_state* s) { return s->t; }
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 long oracle_num_steps(const oracle_state* s) { return s->steps; }

@@ -71,6 +71,8 @@ void oracle_equilibrium_moments(const oracle_state* s, double rho, const double*
                                 double T, double* out /* D+2 */);
 double oracle_time(const oracle_state* s);
 long oracle_num_steps(const oracle_state* s);
+/* OpenMP threads the oracle runs on. */
+int oracle_num_threads(void);
 
 #ifdef __cplusplus
 }

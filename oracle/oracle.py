@@ -25,7 +25,9 @@ QUAD = {"trapezoid": 0, "boole": 1}
 
 def build(force: bool = True) -> str:
     """Compile the oracle into ``oracle/libcdugks_oracle.so``."""
-    if force or not os.path.exists(LIB):
+    stale = not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+        os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "cdugks_oracle.h")))
+    if force or stale:
         tmp = LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
                "-o", tmp, SRC, "-lm"]
@@ -87,8 +89,14 @@ def _load():
         lib.oracle_time.argtypes = [ctypes.c_void_p]
         lib.oracle_num_steps.restype = ctypes.c_long
         lib.oracle_num_steps.argtypes = [ctypes.c_void_p]
+        lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_num_threads.argtypes = []
         _lib = lib
     return _lib
+
+
+def num_threads() -> int:
+    return _load().oracle_num_threads()
 
 
 def _ptr(a: np.ndarray):
@@ -151,10 +159,11 @@ class Oracle:
         p.R = float(prob.get("R", 0.5))
         relax = prob.get("relax", "mu")
         p.relax_mode = 0 if relax == "mu" else 1
-        p.mu_ref = float(prob.get("mu_ref", 1e-3))
-        p.T_ref = float(prob.get("T_ref", 1.0))
+        p.mu_ref = float(prob.get("mu_ref") or 1e-3)
+        p.T_ref = float(prob.get("T_ref") or 1.0)
         p.omega = float(prob.get("omega", 0.5))
-        p.tau = float(prob.get("tau", math.inf))
+        tau = prob.get("tau")
+        p.tau = math.inf if tau is None else float(tau)
         p.dt = float(prob["dt"])
         self._p = p
         self.D = D

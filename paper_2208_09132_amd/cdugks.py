@@ -1,0 +1,283 @@
+"""Python binding of the CDUGKS C ABI (``include/cdugks.h``).
+
+Argument marshalling only: every stage of a time step runs in the HIP kernels
+of ``libcdugks.so``.  PyTorch supplies the device memory (arenas) and the
+stream when a caller wants them; plain use needs only numpy.
+
+The functions keep the C names (``cdugks_init``, ``cdugks_step``, ...); the
+``Solver`` class wraps one context.  Loading fails loudly when the HIP library
+has not been built -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcdugks.so")
+
+OK, PENDING = 0, 1
+ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_NONPHYSICAL, ERR_TOO_LARGE, ERR_BUSY, ERR_UNKNOWN = -1, -2, -3, -4, -5, -6, -7
+BC = {"periodic": 0, "outflow": 1}
+RELAX = {"kn": 0, "mu": 1, "tau": 2}
+QUAD = {"trapezoid": 0, "boole": 1}
+STORE = {"f64": 0, "f32": 1}
+
+ERROR_NAMES = {ERR_INVALID: "ERR_INVALID", ERR_NOMEM: "ERR_NOMEM", ERR_DEVICE: "ERR_DEVICE",
+               ERR_NONPHYSICAL: "ERR_NONPHYSICAL", ERR_TOO_LARGE: "ERR_TOO_LARGE", ERR_BUSY: "ERR_BUSY",
+               ERR_UNKNOWN: "ERR_UNKNOWN"}
+
+
+class CdugksError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class cdugks_space(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3)]
+
+
+class cdugks_velocity(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int64 * 3), ("vmin", ctypes.c_double * 3), ("vmax", ctypes.c_double * 3),
+                ("quadrature", ctypes.c_int)]
+
+
+class cdugks_params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("Pr", ctypes.c_double), ("R", ctypes.c_double),
+                ("omega", ctypes.c_double), ("relax_mode", ctypes.c_int), ("Kn", ctypes.c_double),
+                ("L_ref", ctypes.c_double), ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
+                ("mu_ref", ctypes.c_double), ("tau", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("dt", ctypes.c_double), ("storage", ctypes.c_int), ("velocity_slices", ctypes.c_int)]
+
+
+_lib = None
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def load_library():
+    """Load ``libcdugks.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"CDUGKS HIP library not built: {LIB_PATH} is missing "
+                          "(run __graft_entry__.build() or python -m paper_2208_09132_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "cdugks_required_bytes": (ctypes.c_int, [ctypes.POINTER(cdugks_space), ctypes.POINTER(cdugks_velocity),
+                                                 ctypes.POINTER(cdugks_params), ctypes.POINTER(sz)]),
+        "cdugks_init": (ctypes.c_int, [ctypes.POINTER(cdugks_space), ctypes.POINTER(cdugks_velocity),
+                                       ctypes.POINTER(cdugks_params), _DP, _DP, _DP, vp, vp, sz,
+                                       ctypes.POINTER(vp)]),
+        "cdugks_step": (ctypes.c_int, [vp, i64]),
+        "cdugks_sync": (ctypes.c_int, [vp]),
+        "cdugks_moments": (ctypes.c_int, [vp, _DP, _DP, _DP, ctypes.c_int]),
+        "cdugks_conserved": (ctypes.c_int, [vp, _DP]),
+        "cdugks_distributions": (ctypes.c_int, [vp, _DP, _DP]),
+        "cdugks_info": (ctypes.c_int, [vp, _DP, _DP, ctypes.POINTER(i64)]),
+        "cdugks_profile_phases": (ctypes.c_int, [vp, i64, _DP]),
+        "cdugks_destroy": (None, [vp]),
+        "cdugks_batch_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]),
+        "cdugks_batch_step": (ctypes.c_int, [vp, i64]),
+        "cdugks_batch_destroy": (None, [vp]),
+        "cdugks_server_create": (ctypes.c_int, [sz, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)]),
+        "cdugks_submit": (ctypes.c_int, [vp, ctypes.POINTER(cdugks_space), ctypes.POINTER(cdugks_velocity),
+                                         ctypes.POINTER(cdugks_params), _DP, _DP, _DP, i64,
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+        "cdugks_poll": (ctypes.c_int, [vp, ctypes.c_uint64, _DP, _DP, _DP, _DP, _DP]),
+        "cdugks_server_destroy": (None, [vp]),
+        "cdugks_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load_library().cdugks_last_error().decode()
+
+
+def check(rc: int) -> int:
+    if rc < 0:
+        raise CdugksError(rc, last_error())
+    return rc
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_DP)
+
+
+def describe(prob: dict):
+    """Build the three ABI structs from a workload dict (see workloads.py)."""
+    D = int(prob["dim"])
+    sp = cdugks_space()
+    ve = cdugks_velocity()
+    pa = cdugks_params()
+    sp.dim = D
+    for d in range(3):
+        if d < D:
+            sp.n[d] = int(prob["n"][d])
+            sp.lo[d] = float(prob["lo"][d])
+            sp.hi[d] = float(prob["hi"][d])
+            sp.bc[d] = BC[prob["bc"][d]]
+            ve.nv[d] = int(prob["nv"][d])
+            ve.vmin[d] = float(prob["vmin"][d])
+            ve.vmax[d] = float(prob["vmax"][d])
+        else:
+            sp.n[d] = 1
+            sp.hi[d] = 1.0
+            ve.nv[d] = 1
+    ve.quadrature = QUAD[prob.get("quad", "trapezoid")]
+    pa.gamma = float(prob.get("gamma", 5.0 / 3.0))
+    pa.Pr = float(prob.get("Pr", 2.0 / 3.0))
+    pa.R = float(prob.get("R", 0.5))
+    pa.omega = float(prob.get("omega", 0.5))
+    pa.relax_mode = RELAX[prob.get("relax", "kn")]
+    pa.Kn = float(prob.get("Kn") or 0.0)
+    pa.L_ref = float(prob.get("L_ref") or 0.0)
+    pa.rho_ref = float(prob.get("rho_ref") or 0.0)
+    pa.T_ref = float(prob.get("T_ref") or 0.0)
+    pa.mu_ref = float(prob.get("mu_ref") or 0.0)
+    pa.tau = float(prob.get("tau", math.inf))
+    pa.cfl = float(prob.get("cfl", 0.5))
+    pa.dt = float(prob.get("dt") or 0.0)
+    pa.storage = STORE[prob.get("storage", "f64")]
+    pa.velocity_slices = int(prob.get("velocity_slices", 0))
+    return sp, ve, pa
+
+
+def _fields(prob: dict):
+    D = int(prob["dim"])
+    N = int(np.prod([prob["n"][d] for d in range(D)]))
+    rho = np.ascontiguousarray(prob["rho"], dtype=np.float64).reshape(N)
+    u = np.ascontiguousarray(prob["u"], dtype=np.float64).reshape(D * N)
+    T = np.ascontiguousarray(prob["T"], dtype=np.float64).reshape(N)
+    return D, N, rho, u, T
+
+
+def cdugks_required_bytes(prob: dict) -> int:
+    sp, ve, pa = describe(prob)
+    out = ctypes.c_size_t(0)
+    check(load_library().cdugks_required_bytes(ctypes.byref(sp), ctypes.byref(ve), ctypes.byref(pa),
+                                               ctypes.byref(out)))
+    return out.value
+
+
+def cdugks_init(prob: dict, stream=None, arena=None, arena_bytes: int = 0):
+    sp, ve, pa = describe(prob)
+    _, _, rho, u, T = _fields(prob)
+    h = ctypes.c_void_p()
+    check(load_library().cdugks_init(ctypes.byref(sp), ctypes.byref(ve), ctypes.byref(pa), _ptr(rho), _ptr(u),
+                                     _ptr(T), stream, arena, arena_bytes, ctypes.byref(h)))
+    return h
+
+
+def cdugks_step(ctx, nsteps: int) -> None:
+    check(load_library().cdugks_step(ctx, int(nsteps)))
+
+
+def cdugks_sync(ctx) -> None:
+    check(load_library().cdugks_sync(ctx))
+
+
+def cdugks_destroy(ctx) -> None:
+    load_library().cdugks_destroy(ctx)
+
+
+def _torch_stream_handle():
+    """Handle of torch's current stream; a fresh default-priority stream when
+    that is the null stream (graphs are not captured on the null stream)."""
+    import torch  # plumbing only
+    st = torch.cuda.current_stream()
+    if st.cuda_stream == 0:
+        st = torch.cuda.Stream()
+    return st, ctypes.c_void_p(st.cuda_stream)
+
+
+class Solver:
+    """One problem on the GPU.  ``use_torch`` takes the arena from a torch
+    tensor and the stream from torch's current stream."""
+
+    def __init__(self, prob: dict, use_torch: bool = False, stream=None):
+        self.prob = prob
+        self.D, self.N, _, _, _ = _fields(prob)
+        self.V = int(np.prod([prob["nv"][d] for d in range(self.D)]))
+        self._arena = None
+        self._stream = None
+        arena, nbytes = None, 0
+        if use_torch:
+            import torch
+            nbytes = cdugks_required_bytes(prob)
+            self._arena = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            base = self._arena.data_ptr()
+            arena = ctypes.c_void_p((base + 255) & ~255)
+            if stream is None:
+                self._stream, stream = _torch_stream_handle()
+        self.ctx = cdugks_init(prob, stream=stream, arena=arena, arena_bytes=nbytes)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            cdugks_destroy(self.ctx)
+            self.ctx = None
+        self._arena = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1) -> None:
+        cdugks_step(self.ctx, n)
+
+    def sync(self) -> None:
+        cdugks_sync(self.ctx)
+
+    def moments(self):
+        rho = np.zeros(self.N)
+        u = np.zeros(self.D * self.N)
+        T = np.zeros(self.N)
+        check(load_library().cdugks_moments(self.ctx, _ptr(rho), _ptr(u), _ptr(T), 0))
+        return rho, u.reshape(self.D, self.N), T
+
+    def moments_device(self, rho_ptr: int, u_ptr: int, T_ptr: int) -> None:
+        c = ctypes.cast
+        check(load_library().cdugks_moments(self.ctx, c(rho_ptr, _DP), c(u_ptr, _DP), c(T_ptr, _DP), 1))
+
+    def conserved(self):
+        W = np.zeros(self.N * (self.D + 2))
+        check(load_library().cdugks_conserved(self.ctx, _ptr(W)))
+        return W.reshape(self.N, self.D + 2)
+
+    def distributions(self):
+        g = np.zeros(self.V * self.N)
+        b = np.zeros(self.V * self.N)
+        check(load_library().cdugks_distributions(self.ctx, _ptr(g), _ptr(b)))
+        return g.reshape(self.V, self.N), b.reshape(self.V, self.N)
+
+    def info(self):
+        dt, t = ctypes.c_double(), ctypes.c_double()
+        n = ctypes.c_int64()
+        check(load_library().cdugks_info(self.ctx, ctypes.byref(dt), ctypes.byref(t), ctypes.byref(n)))
+        return dt.value, t.value, n.value
+
+    def profile_phases(self, nsteps: int):
+        """Mean per-step kernel durations (ms) from HIP events on the context's
+        stream: face sums, face closure, cell closure, update."""
+        ms = np.zeros(4)
+        check(load_library().cdugks_profile_phases(self.ctx, int(nsteps), _ptr(ms)))
+        return ms
+
+    @property
+    def dt(self) -> float:
+        return self.info()[0]

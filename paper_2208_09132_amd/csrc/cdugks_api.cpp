@@ -1,0 +1,634 @@
+// Host side of the CDUGKS library: validation, device memory, step
+// orchestration with HIP graphs, and the C ABI declared in include/cdugks.h.
+#include "cdugks.h"
+#include "cdugks_host.h"
+
+#include <algorithm>
+#include <mutex>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace cdg {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(CDUGKS_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// problem set-up
+// ---------------------------------------------------------------------------
+int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_params* pa,
+            const double* rho, Resolved* out) {
+    if (!sp || !ve || !pa || !out) return fail(CDUGKS_ERR_INVALID, "null argument");
+    Resolved r{};
+    const int D = sp->dim;
+    if (D < 1 || D > 3) return fail(CDUGKS_ERR_INVALID, "dim must be 1, 2 or 3 (got %d)", D);
+    r.D = D;
+    r.N = 1;
+    r.NE = 1;
+    r.V = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (d < D) {
+            if (sp->n[d] < 1 || sp->n[d] > (1 << 24)) return fail(CDUGKS_ERR_INVALID, "n[%d] out of range", d);
+            if (!(sp->hi[d] > sp->lo[d])) return fail(CDUGKS_ERR_INVALID, "empty domain along %d", d);
+            if (sp->bc[d] != CDUGKS_BC_PERIODIC && sp->bc[d] != CDUGKS_BC_OUTFLOW)
+                return fail(CDUGKS_ERR_INVALID, "unsupported boundary condition %d along %d", sp->bc[d], d);
+            if (ve->nv[d] < 2 || ve->nv[d] > 4096) return fail(CDUGKS_ERR_INVALID, "nv[%d] must be in [2, 4096]", d);
+            if (!(ve->vmax[d] > ve->vmin[d])) return fail(CDUGKS_ERR_INVALID, "empty velocity box along %d", d);
+            if (ve->quadrature == CDUGKS_QUAD_BOOLE && (ve->nv[d] - 1) % 4 != 0)
+                return fail(CDUGKS_ERR_INVALID, "Boole quadrature needs nv = 4k+1 (nv[%d] = %lld)", d,
+                            (long long)ve->nv[d]);
+            r.n[d] = (int)sp->n[d];
+            r.bc[d] = sp->bc[d];
+            r.ne[d] = r.n[d] + (r.bc[d] == CDUGKS_BC_OUTFLOW ? 1 : 0);
+            r.nv[d] = (int)ve->nv[d];
+            r.dx[d] = (sp->hi[d] - sp->lo[d]) / r.n[d];
+        } else {
+            r.n[d] = r.ne[d] = r.nv[d] = 1;
+            r.bc[d] = 0;
+            r.dx[d] = 1.0;
+        }
+        r.N *= r.n[d];
+        r.NE *= r.ne[d];
+        r.V *= r.nv[d];
+    }
+    if (ve->quadrature != CDUGKS_QUAD_TRAPEZOID && ve->quadrature != CDUGKS_QUAD_BOOLE)
+        return fail(CDUGKS_ERR_INVALID, "unknown quadrature %d", ve->quadrature);
+    if (!(pa->gamma > 1.0) || pa->gamma > 5.0 / 3.0 + 1e-12)
+        return fail(CDUGKS_ERR_INVALID, "gamma must lie in (1, 5/3] (got %g)", pa->gamma);
+    if (!(pa->Pr > 0.0)) return fail(CDUGKS_ERR_INVALID, "Pr must be > 0");
+    if (!(pa->R > 0.0)) return fail(CDUGKS_ERR_INVALID, "R must be > 0");
+    if (pa->storage != CDUGKS_STORE_F64 && pa->storage != CDUGKS_STORE_F32)
+        return fail(CDUGKS_ERR_INVALID, "unknown storage mode %d", pa->storage);
+    r.storage = pa->storage;
+    r.gamma = pa->gamma;
+    r.Pr = pa->Pr;
+    r.R = pa->R;
+    r.omega = pa->omega;
+    r.K = (5.0 - 3.0 * pa->gamma) / (pa->gamma - 1.0);
+    r.c_int = 3.0 - D + r.K;
+
+    // velocity axes: uniform nodes including both end points (Sec. 3.1)
+    r.quad = ve->quadrature;
+    for (int d = 0; d < D; ++d) {
+        r.vmin[d] = ve->vmin[d];
+        r.vmax[d] = ve->vmax[d];
+    }
+    double xi2 = 0.0;
+    for (int d = 0; d < D; ++d) xi2 += std::max(ve->vmin[d] * ve->vmin[d], ve->vmax[d] * ve->vmax[d]);
+    const double xi_max = std::sqrt(xi2);
+    double dx_min = r.dx[0];
+    for (int d = 1; d < D; ++d) dx_min = std::min(dx_min, r.dx[d]);
+    // Sec. 4: dt = alpha dx_min / (2 |xi_max|), alpha in (0, 1]
+    const double dt_bound = dx_min / (2.0 * xi_max);
+    if (pa->dt > 0.0) {
+        if (pa->dt > dt_bound * (1.0 + 1e-12))
+            return fail(CDUGKS_ERR_INVALID, "dt %g above the CFL bound %g", pa->dt, dt_bound);
+        r.dt = pa->dt;
+    } else {
+        if (!(pa->cfl > 0.0) || pa->cfl > 1.0) return fail(CDUGKS_ERR_INVALID, "cfl must lie in (0, 1]");
+        r.dt = pa->cfl * dt_bound;
+    }
+
+    switch (pa->relax_mode) {
+    case CDUGKS_RELAX_KN: {
+        if (!(pa->Kn > 0.0)) return fail(CDUGKS_ERR_INVALID, "Kn must be > 0");
+        double L = pa->L_ref > 0.0 ? pa->L_ref : (sp->hi[0] - sp->lo[0]);
+        double rho_ref = pa->rho_ref;
+        if (!(rho_ref > 0.0)) {
+            if (!rho) return fail(CDUGKS_ERR_INVALID, "rho_ref needed");
+            double s = 0.0;
+            for (long long c = 0; c < r.N; ++c) s += rho[c];
+            rho_ref = s / (double)r.N;
+        }
+        double T_ref = pa->T_ref > 0.0 ? pa->T_ref : 1.0;
+        // hard-sphere mean free path lambda = 16 mu / (5 rho sqrt(2 pi R T))
+        r.mu_ref = 5.0 / 16.0 * pa->Kn * L * rho_ref * std::sqrt(2.0 * M_PI * pa->R * T_ref);
+        r.T_ref = T_ref;
+        r.relax = 0;
+        break;
+    }
+    case CDUGKS_RELAX_MU:
+        if (!(pa->mu_ref > 0.0)) return fail(CDUGKS_ERR_INVALID, "mu_ref must be > 0");
+        r.mu_ref = pa->mu_ref;
+        r.T_ref = pa->T_ref > 0.0 ? pa->T_ref : 1.0;
+        r.relax = 0;
+        break;
+    case CDUGKS_RELAX_TAU:
+        if (!(pa->tau > 0.0)) return fail(CDUGKS_ERR_INVALID, "tau must be > 0 (or +inf)");
+        r.tau_inv = std::isinf(pa->tau) ? 0.0 : 1.0 / pa->tau;
+        r.relax = 1;
+        r.mu_ref = 1.0;
+        r.T_ref = 1.0;
+        break;
+    default:
+        return fail(CDUGKS_ERR_INVALID, "unknown relax mode %d", pa->relax_mode);
+    }
+
+    int t[3];
+    tile_extent(D, t);
+    long long nt1 = 1, nt2 = 1;
+    for (int d = 0; d < 3; ++d) {
+        r.tiles1[d] = (r.ne[d] + t[d] - 1) / t[d];
+        r.tiles2[d] = (r.n[d] + t[d] - 1) / t[d];
+        nt1 *= r.tiles1[d];
+        nt2 *= r.tiles2[d];
+    }
+    // Velocity slices: fill the chip's resident workgroup slots in whole
+    // rounds.  The face-sum split fixes the summation order, so it depends only
+    // on the problem and the device type, never on what else is running.
+    long long R1, R2;
+    resident_slots(D, r.storage, &R1, &R2);
+    auto plan = [&](long long ntiles, long long R) {
+        if (ntiles >= R) return 1LL;
+        long long s = (R + ntiles / 2) / ntiles;
+        return std::max(1LL, s);
+    };
+    int slices = pa->velocity_slices;
+    long long s1 = slices > 0 ? slices : plan(nt1, R1);
+    s1 = std::min<long long>(s1, std::max(1LL, r.V / 2));
+    r.nslices = (int)std::max(1LL, s1);
+    long long s2 = plan(nt2, R2);
+    r.nslices_upd = (int)std::max(1LL, std::min<long long>(s2, r.V));
+
+    // byte plan
+    const size_t es = r.storage == CDUGKS_STORE_F64 ? 8 : 4;
+    const size_t NV = (size_t)r.N * r.V;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    for (int k = 0; k < 2; ++k) {
+        r.off_g[k] = take(NV * es);
+        r.off_b[k] = take(NV * es);
+        r.off_W[k] = take((size_t)(D + 2) * r.N * 8);
+        r.off_P[k] = take((size_t)NPC * r.N * 8);
+    }
+    r.off_FS = take((size_t)r.nslices * D * (2 * D + 3) * r.NE * 8);
+    r.off_FP = take((size_t)D * NFP * r.NE * 8);
+    r.off_G = take((size_t)D * (D + 2) * r.NE * 8);
+    r.off_vel = take((size_t)r.V * NVEL * 8);
+    r.off_axis = take((size_t)2 * (r.nv[0] + r.nv[1] + r.nv[2]) * 8);
+    r.off_err = take(256);
+    r.off_scratch = take((size_t)(D + 2) * r.N * 8);
+    r.bytes = off;
+    *out = r;
+    return CDUGKS_OK;
+}
+
+void resident_slots(int D, int storage, long long* R1, long long* R2) {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    static int cus = -1;
+    static int cache[3][2][2];
+    static bool have[3][2][2];
+    if (cus < 0) {
+        int dev = 0, n = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceCount(&n) == hipSuccess && n > 0 && hipGetDevice(&dev) == hipSuccess &&
+            hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            cus = prop.multiProcessorCount;
+        else
+            cus = 0;
+        (void)hipGetLastError();
+    }
+    int bp[2];
+    for (int u = 0; u < 2; ++u) {
+        if (!have[D - 1][storage][u]) {
+            cache[D - 1][storage][u] = cus > 0 ? tile_blocks_per_cu(D, storage, u == 1) : 0;
+            have[D - 1][storage][u] = true;
+        }
+        bp[u] = cache[D - 1][storage][u];
+    }
+    const long long c = cus > 0 ? cus : 256;
+    *R1 = c * (bp[0] > 0 ? bp[0] : 4);
+    *R2 = c * (bp[1] > 0 ? bp[1] : 4);
+}
+
+void velocity_tables(const Resolved& r, std::vector<double>& vel, std::vector<double>& axis) {
+    const int D = r.D;
+    std::vector<double> nodes[3], wts[3];
+    for (int d = 0; d < 3; ++d) {
+        int nv = r.nv[d];
+        nodes[d].assign(nv, 0.0);
+        wts[d].assign(nv, 1.0);
+        if (d >= D) continue;
+        double h = (r.vmax[d] - r.vmin[d]) / (nv - 1);
+        for (int m = 0; m < nv; ++m) nodes[d][m] = r.vmin[d] + m * h;
+        if (r.quad == CDUGKS_QUAD_BOOLE) {
+            static const double c[5] = {7.0, 32.0, 12.0, 32.0, 7.0};
+            std::fill(wts[d].begin(), wts[d].end(), 0.0);
+            for (int p0 = 0; p0 + 4 < nv; p0 += 4)
+                for (int k = 0; k < 5; ++k) wts[d][p0 + k] += c[k] * 2.0 * h / 45.0;
+        } else {
+            std::fill(wts[d].begin(), wts[d].end(), h);
+            wts[d][0] = wts[d][nv - 1] = 0.5 * h;
+        }
+    }
+    vel.assign((size_t)r.V * NVEL, 0.0);
+    for (long long i = 0; i < r.V; ++i) {
+        long long rem = i;
+        int m[3];
+        for (int d = 0; d < 3; ++d) {
+            m[d] = (int)(rem % r.nv[d]);
+            rem /= r.nv[d];
+        }
+        double* v = vel.data() + i * NVEL;
+        double w = 1.0, x2 = 0.0;
+        for (int d = 0; d < D; ++d) {
+            double x = nodes[d][m[d]];
+            v[VE_XI0 + d] = x;
+            w *= wts[d][m[d]];
+            x2 += x * x;
+            v[VE_LAM0 + d] = 0.5 * r.dt * x / r.dx[d];
+        }
+        v[VE_W] = w;
+        v[VE_HX2] = 0.5 * x2;
+    }
+    axis.clear();
+    for (int d = 0; d < 3; ++d) axis.insert(axis.end(), nodes[d].begin(), nodes[d].end());
+    for (int d = 0; d < 3; ++d) axis.insert(axis.end(), wts[d].begin(), wts[d].end());
+}
+
+void fill_problem(const Resolved& r, char* base, Problem& P) {
+    std::memset(&P, 0, sizeof P);
+    P.D = r.D;
+    P.storage = r.storage;
+    P.nslices = r.nslices;
+    P.nslices_upd = r.nslices_upd;
+    P.relax = r.relax;
+    for (int d = 0; d < 3; ++d) {
+        P.n[d] = r.n[d];
+        P.ne[d] = r.ne[d];
+        P.bc[d] = r.bc[d];
+        P.nv[d] = r.nv[d];
+        P.tiles1[d] = r.tiles1[d];
+        P.tiles2[d] = r.tiles2[d];
+        P.dx[d] = r.dx[d];
+        P.inv_dx[d] = 1.0 / r.dx[d];
+    }
+    P.V = (int)r.V;
+    P.N = r.N;
+    P.NE = r.NE;
+    P.dt = r.dt;
+    P.gamma = r.gamma;
+    P.Pr = r.Pr;
+    P.R = r.R;
+    P.c_int = r.c_int;
+    P.omega = r.omega;
+    P.mu_ref = r.mu_ref;
+    P.T_ref = r.T_ref;
+    P.tau_inv = r.tau_inv;
+    P.vel = (const double*)(base + r.off_vel);
+    P.axis_xi = (const double*)(base + r.off_axis);
+    P.axis_w = P.axis_xi + (r.nv[0] + r.nv[1] + r.nv[2]);
+    P.FS = (double*)(base + r.off_FS);
+    P.FP = (double*)(base + r.off_FP);
+    P.G = (double*)(base + r.off_G);
+    P.err = (int*)(base + r.off_err);
+}
+
+void set_pingpong(Problem& P, const Resolved& r, char* base, int cur) {
+    int nxt = 1 - cur;
+    P.g_in = base + r.off_g[cur];
+    P.b_in = base + r.off_b[cur];
+    P.g_out = base + r.off_g[nxt];
+    P.b_out = base + r.off_b[nxt];
+    P.W_in = (const double*)(base + r.off_W[cur]);
+    P.W_out = (double*)(base + r.off_W[nxt]);
+    P.P_in = (const double*)(base + r.off_P[cur]);
+    P.P_out = (double*)(base + r.off_P[nxt]);
+}
+
+hipError_t enqueue_step(const Problem& P, hipStream_t s) {
+    hipError_t e;
+    if ((e = launch_face_sums(P, s)) != hipSuccess) return e;
+    if ((e = launch_face_close(P, s)) != hipSuccess) return e;
+    if ((e = launch_cell_close(P, s)) != hipSuccess) return e;
+    return launch_update(P, s);
+}
+
+// Capture `steps` consecutive steps starting from buffer parity `cur` into a
+// graph (kernel nodes only).
+static hipError_t capture_steps(cdugks_ctx* c, int cur, int steps, hipGraphExec_t* exec) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    Problem P = c->P;
+    int k = cur;
+    hipError_t le = hipSuccess;
+    for (int s = 0; s < steps && le == hipSuccess; ++s) {
+        set_pingpong(P, c->r, c->base, k);
+        le = enqueue_step(P, c->stream);
+        k = 1 - k;
+    }
+    e = hipStreamEndCapture(c->stream, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return le;
+    }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
+}
+
+}  // namespace cdg
+
+using namespace cdg;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* cdugks_last_error(void) { return g_last_error.c_str(); }
+
+int cdugks_required_bytes(const cdugks_space* space, const cdugks_velocity* vel,
+                          const cdugks_params* params, size_t* bytes) {
+    if (!bytes) return fail(CDUGKS_ERR_INVALID, "null bytes pointer");
+    cdugks_params p = *params;
+    if (p.relax_mode == CDUGKS_RELAX_KN && !(p.rho_ref > 0.0)) p.rho_ref = 1.0;  // size does not depend on it
+    Resolved r;
+    int rc = resolve(space, vel, &p, nullptr, &r);
+    if (rc) return rc;
+    *bytes = r.bytes;
+    return CDUGKS_OK;
+}
+
+int cdugks_init(const cdugks_space* space, const cdugks_velocity* vel, const cdugks_params* params,
+                const double* rho, const double* u, const double* T, void* hip_stream, void* arena,
+                size_t arena_bytes, cdugks_ctx** out) {
+    if (!out) return fail(CDUGKS_ERR_INVALID, "null output pointer");
+    *out = nullptr;
+    if (!rho || !u || !T) return fail(CDUGKS_ERR_INVALID, "null moment array");
+    Resolved r;
+    int rc = resolve(space, vel, params, rho, &r);
+    if (rc) return rc;
+    for (long long c = 0; c < r.N; ++c) {
+        if (!(rho[c] > 0.0) || !std::isfinite(rho[c])) return fail(CDUGKS_ERR_INVALID, "rho[%lld] must be > 0", c);
+        if (!(T[c] > 0.0) || !std::isfinite(T[c])) return fail(CDUGKS_ERR_INVALID, "T[%lld] must be > 0", c);
+    }
+    for (long long k = 0; k < (long long)r.D * r.N; ++k)
+        if (!std::isfinite(u[k])) return fail(CDUGKS_ERR_INVALID, "u[%lld] is not finite", k);
+
+    cdugks_ctx* c = new (std::nothrow) cdugks_ctx();
+    if (!c) return fail(CDUGKS_ERR_NOMEM, "host allocation failed");
+    c->r = r;
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t e;
+    if (!c->stream) {
+        // a private stream (default priority): graphs cannot be captured on
+        // the legacy null stream
+        if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
+            delete c;
+            return hip_fail(e, "stream create");
+        }
+        c->own_stream = true;
+    }
+    if (arena) {
+        if (arena_bytes < r.bytes) {
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            delete c;
+            return fail(CDUGKS_ERR_INVALID, "arena of %zu bytes is smaller than the %zu required", arena_bytes,
+                        r.bytes);
+        }
+        if (((uintptr_t)arena & 255) != 0) {
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            delete c;
+            return fail(CDUGKS_ERR_INVALID, "arena must be 256-byte aligned");
+        }
+        c->base = (char*)arena;
+        c->own_memory = false;
+    } else {
+        void* p = nullptr;
+        e = hipMalloc(&p, r.bytes);
+        if (e != hipSuccess) {
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            delete c;
+            (void)hipGetLastError();
+            return fail(CDUGKS_ERR_NOMEM, "hipMalloc of %zu bytes failed", r.bytes);
+        }
+        c->base = (char*)p;
+        c->own_memory = true;
+    }
+    fill_problem(r, c->base, c->P);
+
+    std::vector<double> veltab, axis;
+    velocity_tables(r, veltab, axis);
+    // moments staged in the scratch region for the init kernel
+    std::vector<double> stage((size_t)(r.D + 2) * r.N);
+    std::memcpy(stage.data(), rho, sizeof(double) * r.N);
+    std::memcpy(stage.data() + r.N, u, sizeof(double) * r.D * r.N);
+    std::memcpy(stage.data() + (size_t)(r.D + 1) * r.N, T, sizeof(double) * r.N);
+    double* scratch = (double*)(c->base + r.off_scratch);
+    int zero[64] = {0};
+    if ((e = hipMemcpyAsync(c->base + r.off_vel, veltab.data(), veltab.size() * 8, hipMemcpyHostToDevice,
+                            c->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(c->base + r.off_axis, axis.data(), axis.size() * 8, hipMemcpyHostToDevice,
+                            c->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(scratch, stage.data(), stage.size() * 8, hipMemcpyHostToDevice, c->stream)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(c->base + r.off_err, zero, sizeof zero, hipMemcpyHostToDevice, c->stream)) !=
+            hipSuccess) {
+        cdugks_destroy(c);
+        return hip_fail(e, "upload");
+    }
+    c->cur = 0;
+    Problem P = c->P;
+    set_pingpong(P, r, c->base, 0);
+    if ((e = launch_init(P, scratch, scratch + r.N, scratch + (size_t)(r.D + 1) * r.N, c->stream)) !=
+        hipSuccess) {
+        cdugks_destroy(c);
+        return hip_fail(e, "init kernels");
+    }
+    // host staging buffers must outlive the async copies
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) {
+        cdugks_destroy(c);
+        return hip_fail(e, "init synchronize");
+    }
+    int flag = 0;
+    if ((e = hipMemcpy(&flag, c->base + r.off_err, sizeof flag, hipMemcpyDeviceToHost)) != hipSuccess) {
+        cdugks_destroy(c);
+        return hip_fail(e, "error flag read");
+    }
+    if (flag) {
+        cdugks_destroy(c);
+        return fail(CDUGKS_ERR_NONPHYSICAL, "non-physical initial state");
+    }
+    *out = c;
+    return CDUGKS_OK;
+}
+
+int cdugks_step(cdugks_ctx* c, int64_t nsteps) {
+    if (!c) return fail(CDUGKS_ERR_INVALID, "null context");
+    if (nsteps < 0) return fail(CDUGKS_ERR_INVALID, "negative step count");
+    if (c->sticky) return fail(c->sticky, "context is in an error state");
+    if (c->in_batch) return fail(CDUGKS_ERR_BUSY, "context belongs to a batch");
+    hipError_t e;
+    int64_t left = nsteps;
+    // chunk graphs of CHUNK steps, built lazily per starting parity
+    while (left >= ctx_chunk) {
+        hipGraphExec_t& ge = c->graph[c->cur];
+        if (!ge && (e = capture_steps(c, c->cur, ctx_chunk, &ge)) != hipSuccess) return hip_fail(e, "graph capture");
+        if ((e = hipGraphLaunch(ge, c->stream)) != hipSuccess) return hip_fail(e, "graph launch");
+        left -= ctx_chunk;
+        if (ctx_chunk % 2) c->cur = 1 - c->cur;
+        c->steps += ctx_chunk;
+    }
+    for (; left > 0; --left) {
+        Problem P = c->P;
+        set_pingpong(P, c->r, c->base, c->cur);
+        if ((e = enqueue_step(P, c->stream)) != hipSuccess) return hip_fail(e, "step launch");
+        c->cur = 1 - c->cur;
+        c->steps += 1;
+    }
+    return CDUGKS_OK;
+}
+
+int cdugks_sync(cdugks_ctx* c) {
+    if (!c) return fail(CDUGKS_ERR_INVALID, "null context");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->sticky = CDUGKS_ERR_DEVICE;
+        return hip_fail(e, "stream synchronize");
+    }
+    int flag = 0;
+    e = hipMemcpy(&flag, c->base + c->r.off_err, sizeof flag, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        c->sticky = CDUGKS_ERR_DEVICE;
+        return hip_fail(e, "error flag read");
+    }
+    if (flag) c->sticky = CDUGKS_ERR_NONPHYSICAL;
+    if (c->sticky) return fail(c->sticky, "non-physical state reached (rho <= 0, T <= 0 or non-finite)");
+    return CDUGKS_OK;
+}
+
+int cdugks_moments(cdugks_ctx* c, double* rho, double* u, double* T, int device_ptrs) {
+    if (!c || !rho || !u || !T) return fail(CDUGKS_ERR_INVALID, "null argument");
+    const Resolved& r = c->r;
+    hipError_t e;
+    const double* W = (const double*)(c->base + r.off_W[c->cur]);
+    if (device_ptrs) {
+        if ((e = launch_moments(c->P, W, rho, u, T, c->stream)) != hipSuccess) return hip_fail(e, "moments");
+        return c->sticky ? fail(c->sticky, "context is in an error state") : CDUGKS_OK;
+    }
+    double* s = (double*)(c->base + r.off_scratch);
+    if ((e = launch_moments(c->P, W, s, s + r.N, s + (size_t)(r.D + 1) * r.N, c->stream)) != hipSuccess)
+        return hip_fail(e, "moments");
+    int rc = cdugks_sync(c);
+    if (rc) return rc;
+    if ((e = hipMemcpy(rho, s, sizeof(double) * r.N, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(u, s + r.N, sizeof(double) * r.D * r.N, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(T, s + (size_t)(r.D + 1) * r.N, sizeof(double) * r.N, hipMemcpyDeviceToHost)) !=
+            hipSuccess)
+        return hip_fail(e, "moments copy");
+    return CDUGKS_OK;
+}
+
+int cdugks_conserved(cdugks_ctx* c, double* W) {
+    if (!c || !W) return fail(CDUGKS_ERR_INVALID, "null argument");
+    int rc = cdugks_sync(c);
+    if (rc) return rc;
+    const Resolved& r = c->r;
+    std::vector<double> tmp((size_t)(r.D + 2) * r.N);
+    hipError_t e = hipMemcpy(tmp.data(), c->base + r.off_W[c->cur], tmp.size() * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "W copy");
+    for (long long cc = 0; cc < r.N; ++cc)
+        for (int k = 0; k < r.D + 2; ++k) W[cc * (r.D + 2) + k] = tmp[(size_t)k * r.N + cc];
+    return CDUGKS_OK;
+}
+
+int cdugks_distributions(cdugks_ctx* c, double* g, double* b) {
+    if (!c || !g || !b) return fail(CDUGKS_ERR_INVALID, "null argument");
+    int rc = cdugks_sync(c);
+    if (rc) return rc;
+    const Resolved& r = c->r;
+    size_t n = (size_t)r.N * r.V;
+    double* tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, n * 8);
+    if (e != hipSuccess) return hip_fail(e, "temporary allocation");
+    double* outs[2] = {g, b};
+    size_t offs[2] = {r.off_g[c->cur], r.off_b[c->cur]};
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        e = launch_to_f64(c->P, c->base + offs[k], tmp, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess) e = hipMemcpy(outs[k], tmp, n * 8, hipMemcpyDeviceToHost);
+    }
+    (void)hipFree(tmp);
+    return e == hipSuccess ? CDUGKS_OK : hip_fail(e, "distribution copy");
+}
+
+int cdugks_info(cdugks_ctx* c, double* dt, double* t, int64_t* steps) {
+    if (!c) return fail(CDUGKS_ERR_INVALID, "null context");
+    if (dt) *dt = c->r.dt;
+    if (t) *t = c->r.dt * (double)c->steps;
+    if (steps) *steps = c->steps;
+    return CDUGKS_OK;
+}
+
+int cdugks_profile_phases(cdugks_ctx* c, int64_t nsteps, double* ms) {
+    if (!c || !ms || nsteps <= 0) return fail(CDUGKS_ERR_INVALID, "bad argument");
+    if (c->sticky) return fail(c->sticky, "context is in an error state");
+    hipEvent_t ev[5];
+    for (int k = 0; k < 5; ++k)
+        if (hipEventCreate(&ev[k]) != hipSuccess) return fail(CDUGKS_ERR_DEVICE, "event create");
+    double acc[4] = {0, 0, 0, 0};
+    hipError_t e = hipSuccess;
+    for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
+        Problem P = c->P;
+        set_pingpong(P, c->r, c->base, c->cur);
+        e = hipEventRecord(ev[0], c->stream);
+        if (e == hipSuccess) e = launch_face_sums(P, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+        if (e == hipSuccess) e = launch_face_close(P, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
+        if (e == hipSuccess) e = launch_cell_close(P, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
+        if (e == hipSuccess) e = launch_update(P, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[4], c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
+        for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+            acc[k] += t;
+        }
+        c->cur = 1 - c->cur;
+        c->steps += 1;
+    }
+    for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
+    if (e != hipSuccess) return hip_fail(e, "profiled step");
+    for (int k = 0; k < 4; ++k) ms[k] = acc[k] / (double)nsteps;
+    return cdugks_sync(c);
+}
+
+void cdugks_destroy(cdugks_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < 2; ++k)
+        if (c->graph[k]) (void)hipGraphExecDestroy(c->graph[k]);
+    if (c->own_memory && c->base) (void)hipFree(c->base);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// Host-side internals of the CDUGKS library (contexts, byte plans).
+#pragma once
+
+#include <cstdarg>
+#include <cstddef>
+#include <vector>
+
+#include "cdugks.h"
+#include "cdugks_internal.h"
+
+namespace cdg {
+
+// Everything derived from the user's description of a problem.
+struct Resolved {
+    int D;
+    int n[3], ne[3], bc[3], nv[3];
+    int tiles1[3], tiles2[3];
+    long long N, NE, V;
+    double dx[3];
+    double vmin[3], vmax[3];
+    int quad;
+    int storage;
+    int nslices, nslices_upd;
+    int relax;
+    double dt, gamma, Pr, R, omega, K, c_int, mu_ref, T_ref, tau_inv;
+    // byte offsets inside the problem's device block
+    size_t off_g[2], off_b[2], off_W[2], off_P[2];
+    size_t off_FS, off_FP, off_G, off_vel, off_axis, off_err, off_scratch;
+    size_t bytes;
+};
+
+// Steps per captured graph of a single context.
+constexpr int ctx_chunk = 50;
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_params* pa,
+            const double* rho, Resolved* out);
+void resident_slots(int D, int storage, long long* R1, long long* R2);
+void velocity_tables(const Resolved& r, std::vector<double>& vel, std::vector<double>& axis);
+void fill_problem(const Resolved& r, char* base, Problem& P);
+void set_pingpong(Problem& P, const Resolved& r, char* base, int cur);
+hipError_t enqueue_step(const Problem& P, hipStream_t s);
+
+}  // namespace cdg
+
+struct cdugks_ctx {
+    cdg::Resolved r;
+    cdg::Problem P;       // descriptor without the ping-pong pointers
+    hipStream_t stream = nullptr;
+    bool own_stream = false;  // created here when the caller passes NULL
+    char* base = nullptr;
+    bool own_memory = false;
+    int cur = 0;          // buffer parity holding the current state
+    int64_t steps = 0;
+    int sticky = 0;
+    bool in_batch = false;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+};

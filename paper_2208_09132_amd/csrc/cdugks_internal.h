@@ -1,0 +1,107 @@
+// Internal declarations shared by the kernels and the host side of the
+// CDUGKS library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cdg {
+
+// Per-cell coefficient set (structure of arrays, [NPC][N]), computed from W:
+//   A      = rho (2 pi R T)^(-D/2)        Maxwellian prefactor (eq. geq)
+//   INV2RT = 1 / (2 R T)
+//   CRT2   = (3 - D + K) R T / 2           so b_eq = (|xi|^2/2 + CRT2) g_eq (eq. beq)
+//   BETA   = (dt/4) / tau_g               = (h/2)/tau_g, h = dt/2
+//   BETAB  = (dt/4) / tau_b
+//   ETA    = (dt/4) / tau_bg              = (dt/4)(Pr - 1)/tau_g
+//   HU2    = |u|^2 / 2
+//   U0..U2 = bulk velocity
+enum { PC_A = 0, PC_INV2RT, PC_CRT2, PC_BETA, PC_BETAB, PC_ETA, PC_HU2, PC_U0, NPC = PC_U0 + 3 };
+
+// Per-face coefficient set ([D][NFP][NE]), computed from the face W:
+//   A, INV2RT, CRT2, HU2, U0..U2 as above at the face, plus the inversion of
+//   eq. phibar:  g = IG * gbar + BG * g_eq,
+//                b = IB * bbar + BB * b_eq + EB * Z * (g - g_eq)
+enum { PF_A = 0, PF_INV2RT, PF_CRT2, PF_IG, PF_BG, PF_IB, PF_BB, PF_EB, PF_HU2, PF_U0,
+       NFP = PF_U0 + 3 };
+
+// Per-velocity constants ([V][NVEL]): xi, weight, |xi|^2/2 and the Courant-like
+// numbers lambda_d = (dt/2) xi_d / dx_d.
+enum { VE_XI0 = 0, VE_W = 3, VE_HX2 = 4, VE_LAM0 = 5, NVEL = 8 };
+
+constexpr int MAX_NSUM = 9;  // 2D+3 face sums for D = 3
+
+// Device-side description of one problem.  Pointers are device addresses.
+struct Problem {
+    int D;
+    int storage;       // 0 = f64, 1 = f32
+    int nslices;       // velocity slices of the face-sum kernel (fixes the summation order)
+    int nslices_upd;   // velocity slices of the update kernel (throughput only)
+    int relax;         // 0: mu law, 1: constant tau
+    int n[3];          // cells per dimension (1 when unused)
+    int ne[3];         // extended (face) grid: n + 1 for outflow dims
+    int bc[3];         // 0 periodic, 1 outflow
+    int nv[3];
+    int V;
+    int tiles1[3];     // tiles per dimension over the face grid (face-sum kernel)
+    int tiles2[3];     // tiles per dimension over the cells (update kernel)
+    long long N, NE;
+    double dx[3], inv_dx[3];
+    double dt, gamma, Pr, R, c_int, omega, mu_ref, T_ref, tau_inv;
+    const double* vel;    // [V][NVEL]
+    const double* axis_xi;  // concatenated 1-D nodes, offsets 0, nv0, nv0+nv1
+    const double* axis_w;   // concatenated 1-D weights
+    // ping-pong state: *_in read, *_out written
+    const void* g_in; const void* b_in; void* g_out; void* b_out;
+    const double* W_in; double* W_out;
+    const double* P_in; double* P_out;
+    double* FS;   // face partial sums [nslices][D][2D+3][NE]
+    double* FP;   // face coefficients [D][NFP][NE]
+    double* G;    // flux moments [D][D+2][NE]
+    int* err;     // sticky non-physical flag
+};
+
+// One workgroup's assignment in a batched launch.
+struct WorkItem {
+    int prob;     // index into the problem table
+    int tile;     // linear tile index
+    int slice;    // velocity slice
+    int pad;
+};
+
+// Launchers (stream-ordered).  Single-problem forms take the descriptor by
+// value; batched forms read descriptors and items from device memory.
+hipError_t launch_init(const Problem& P, const double* rho, const double* u, const double* T,
+                       hipStream_t s);
+hipError_t launch_face_sums(const Problem& P, hipStream_t s);
+hipError_t launch_face_close(const Problem& P, hipStream_t s);
+hipError_t launch_cell_close(const Problem& P, hipStream_t s);
+hipError_t launch_update(const Problem& P, hipStream_t s);
+hipError_t launch_moments(const Problem& P, const double* W, double* rho, double* u, double* T,
+                          hipStream_t s);
+hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStream_t s);
+
+// Batched: one launch per phase across problems.  `items` lists the work of
+// the tile kernels (face sums / update); `cells` and `faces` are prefix offsets
+// (in threads) for the per-cell and per-face kernels; dims counts problems per
+// spatial dimension so that each launch runs one kernel instantiation.
+hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems,
+                                    int dim, int storage, hipStream_t s);
+hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, int nitems,
+                                 int dim, int storage, hipStream_t s);
+hipError_t launch_face_close_batched(const Problem* probs, const long long* offsets, int nprob,
+                                     long long total, hipStream_t s);
+hipError_t launch_cell_close_batched(const Problem* probs, const long long* offsets, int nprob,
+                                     long long total, hipStream_t s);
+
+// Resident workgroups per CU of the tile kernels (0 when no device answers).
+int tile_blocks_per_cu(int D, int storage, bool update);
+
+// Tile extents per dimension (256 cells per workgroup).
+inline void tile_extent(int D, int t[3]) {
+    if (D == 1) { t[0] = 256; t[1] = 1; t[2] = 1; }
+    else if (D == 2) { t[0] = 16; t[1] = 16; t[2] = 1; }
+    else { t[0] = 8; t[1] = 8; t[2] = 4; }
+}
+
+}  // namespace cdg

@@ -1,0 +1,131 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (relative; u normwise, scaled by max(max|u|, sound speed at T=1)):
+  FP64 storage  1e-12
+  FP32 storage  1e-5
+Cases span several tiles with ragged tails, odd velocity counts (a zero
+velocity), outflow and periodic boundaries, Pr = 1, free streaming, and the
+full Kelvin-Helmholtz size in the launch configuration the benchmark times.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2208_09132_amd import cdugks as cd
+from paper_2208_09132_amd import workloads as wl
+from tests.helpers import make_oracle, moment_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_run(prob, steps):
+    s = cd.Solver(prob)
+    s.step(steps)
+    m = s.moments()
+    dt = s.dt
+    s.close()
+    return m, dt
+
+
+def oracle_run(prob, dt, steps):
+    o = make_oracle(prob, dt=dt)
+    assert o.step(steps) == 0
+    return o.moments()
+
+
+def check_parity(prob, steps, tol):
+    _log(f"parity: dim={prob['dim']} n={prob['n']} nv={prob['nv']} bc={prob['bc']} storage={prob.get('storage')} steps={steps}")
+    got, dt = gpu_run(prob, steps)
+    ref = oracle_run(prob, dt, steps)
+    errs = moment_errors(ref, got, prob.get("gamma", 5.0 / 3.0), prob.get("R", 0.5))
+    _log(f"  errors rho/u/T = {errs}")
+    assert max(errs) <= tol, errs
+    return errs
+
+
+def test_sod_full_run_fp64():
+    p = wl.sod()
+    check_parity(p, p["steps"], 1e-12)
+
+
+def test_1d_periodic_ragged_odd_velocities():
+    p = wl.random_fourier(1, [300], [33], wl.SplitMix64(41), amp=0.2, Kn=1e-2, Pr=2.0)
+    check_parity(p, 30, 1e-12)
+
+
+def test_2d_kelvin_helmholtz_reduced_fp64():
+    p = wl.kelvin_helmholtz(n=40, nv=12)
+    check_parity(p, 20, 1e-12)
+
+
+def test_2d_outflow_rectangular_odd_velocities():
+    p = wl.random_fourier(2, [37, 21], [9, 10], wl.SplitMix64(5), amp=0.2, Kn=3e-2)
+    p["bc"] = ["outflow", "periodic"]
+    check_parity(p, 15, 1e-12)
+
+
+def test_2d_prandtl_one_and_free_streaming():
+    p = wl.random_fourier(2, [20, 18], [10, 10], wl.SplitMix64(8), amp=0.2, Kn=1e-2, Pr=1.0)
+    check_parity(p, 10, 1e-12)
+    q = wl.random_fourier(2, [20, 18], [10, 10], wl.SplitMix64(8), amp=0.2, relax="tau", tau=math.inf)
+    check_parity(q, 10, 1e-12)
+
+
+def test_3d_small_fp64():
+    p = wl.random_fourier(3, [10, 9, 12], [6, 6, 6], wl.SplitMix64(3), amp=0.2, Kn=1e-2)
+    check_parity(p, 5, 1e-12)
+    q = wl.random_fourier(3, [9, 9, 9], [5, 5, 5], wl.SplitMix64(4), amp=0.2, Kn=1e-1)
+    q["bc"] = ["periodic", "outflow", "periodic"]
+    check_parity(q, 4, 1e-12)
+
+
+def test_fp32_storage_within_1e5():
+    p = wl.kelvin_helmholtz(n=40, nv=12, storage="f32")
+    check_parity(p, 20, 1e-5)
+    q = wl.shear3d(n=12, nv=8, Kn=1e-1, storage="f32")
+    check_parity(q, 10, 1e-5)
+
+
+def test_velocity_slicing_does_not_change_results():
+    p = wl.kelvin_helmholtz(n=32, nv=12)
+    ms = []
+    for sl in (1, 3, 16):
+        q = dict(p, velocity_slices=sl)
+        ms.append(gpu_run(q, 6)[0])
+    for m in ms[1:]:
+        assert max(moment_errors(ms[0], m)) <= 1e-13
+
+
+def test_kelvin_helmholtz_full_size_one_step_fp64():
+    """Benchmark configuration (256^2 cells x 28^2 velocities, FP64), same
+    launch shape as bench.py: one step against the oracle."""
+    p = wl.kelvin_helmholtz()
+    check_parity(p, 1, 1e-12)
+
+
+def test_kelvin_helmholtz_full_size_conservation_and_stationarity():
+    p = wl.kelvin_helmholtz()
+    s = cd.Solver(p)
+    W0 = s.conserved().sum(axis=0)
+    s.step(20)
+    W1 = s.conserved().sum(axis=0)
+    s.close()
+    assert np.max(np.abs(W1 - W0)) <= 1e-13 * np.max(np.abs(W0)) * math.sqrt(20) * 10
+    u = dict(p)
+    N = 256 * 256
+    u["rho"] = np.full(N, 1.5)
+    u["T"] = np.full(N, 2.0)
+    u["u"] = np.stack([np.full(N, 0.3), np.full(N, -0.2)])
+    s = cd.Solver(u)
+    Wa = s.conserved()
+    s.step(4)
+    Wb = s.conserved()
+    s.close()
+    assert np.array_equal(Wa, Wb)
