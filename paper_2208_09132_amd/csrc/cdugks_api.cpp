@@ -144,13 +144,12 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
 
     int t[3];
     tile_extent(D, t);
-    long long nt1 = 1, nt2 = 1;
+    long long nt1 = 1;
     for (int d = 0; d < 3; ++d) {
         r.tiles1[d] = (r.ne[d] + t[d] - 1) / t[d];
-        r.tiles2[d] = (r.n[d] + t[d] - 1) / t[d];
         nt1 *= r.tiles1[d];
-        nt2 *= r.tiles2[d];
     }
+    const long long nt2 = (r.N + 255) / 256;  // update blocks of 256 cells
     // Velocity slices: fill the chip's resident workgroup slots in whole
     // rounds.  The face-sum split fixes the summation order, so it depends only
     // on the problem and the device type, never on what else is running.
@@ -183,6 +182,7 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
         r.off_W[k] = take((size_t)(D + 2) * r.N * 8);
         r.off_P[k] = take((size_t)NPC * r.N * 8);
     }
+    r.off_FV = take((size_t)D * 2 * r.V * r.NE * es);
     r.off_FS = take((size_t)r.nslices * D * (2 * D + 3) * r.NE * 8);
     r.off_FP = take((size_t)D * NFP * r.NE * 8);
     r.off_G = take((size_t)D * (D + 2) * r.NE * 8);
@@ -282,7 +282,6 @@ void fill_problem(const Resolved& r, char* base, Problem& P) {
         P.bc[d] = r.bc[d];
         P.nv[d] = r.nv[d];
         P.tiles1[d] = r.tiles1[d];
-        P.tiles2[d] = r.tiles2[d];
         P.dx[d] = r.dx[d];
         P.inv_dx[d] = 1.0 / r.dx[d];
     }
@@ -301,6 +300,7 @@ void fill_problem(const Resolved& r, char* base, Problem& P) {
     P.vel = (const double*)(base + r.off_vel);
     P.axis_xi = (const double*)(base + r.off_axis);
     P.axis_w = P.axis_xi + (r.nv[0] + r.nv[1] + r.nv[2]);
+    P.FV = base + r.off_FV;
     P.FS = (double*)(base + r.off_FS);
     P.FP = (double*)(base + r.off_FP);
     P.G = (double*)(base + r.off_G);

@@ -44,7 +44,6 @@ struct Problem {
     int nv[3];
     int V;
     int tiles1[3];     // tiles per dimension over the face grid (face-sum kernel)
-    int tiles2[3];     // tiles per dimension over the cells (update kernel)
     long long N, NE;
     double dx[3], inv_dx[3];
     double dt, gamma, Pr, R, c_int, omega, mu_ref, T_ref, tau_inv;
@@ -55,6 +54,7 @@ struct Problem {
     const void* g_in; const void* b_in; void* g_out; void* b_out;
     const double* W_in; double* W_out;
     const double* P_in; double* P_out;
+    void* FV;     // face values phi_bar [D][2][V][NE], storage precision
     double* FS;   // face partial sums [nslices][D][2D+3][NE]
     double* FP;   // face coefficients [D][NFP][NE]
     double* G;    // flux moments [D][D+2][NE]
@@ -64,7 +64,7 @@ struct Problem {
 // One workgroup's assignment in a batched launch.
 struct WorkItem {
     int prob;     // index into the problem table
-    int tile;     // linear tile index
+    int tile;     // face sums: linear tile index; update: block of 256 cells
     int slice;    // velocity slice
     int pad;
 };
@@ -94,7 +94,8 @@ hipError_t launch_face_close_batched(const Problem* probs, const long long* offs
 hipError_t launch_cell_close_batched(const Problem* probs, const long long* offsets, int nprob,
                                      long long total, hipStream_t s);
 
-// Resident workgroups per CU of the tile kernels (0 when no device answers).
+// Resident workgroups per CU of the face-sum (update = false) or update kernel
+// (0 when no device answers).
 int tile_blocks_per_cu(int D, int storage, bool update);
 
 // Tile extents per dimension (256 cells per workgroup).

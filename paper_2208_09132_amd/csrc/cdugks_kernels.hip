@@ -12,19 +12,22 @@
 //   face_sums  (tile kernel) : quarter-step field phi_bar_plus (eq. phibarplus),
 //                              Van Leer slopes (eq. VanLeer) and slopes of slopes,
 //                              face value at the characteristic foot (eq. relation),
-//                              and per-face velocity sums -> partial sums per slice
+//                              stored per (face, velocity), and per-face velocity
+//                              sums -> partial sums per slice
 //   face_close (per face)    : face W (eqs. rhobar..rhoEbar), face equilibrium and
 //                              relaxation, inversion coefficients (eq. phibar), and
 //                              the flux moments in closed form
 //   cell_close (per cell)    : W^{n+1} from the flux moments (eqs. rhoupdate..
 //                              rhoEupdate, outward-flux sign), cell coefficients at n+1
-//   update     (tile kernel) : face values again, inversion, microflux (eq. flux),
-//                              and phi^{n+1} (eq. phiupdate)
+//   update     (streaming)   : stored face values, inversion (eq. phibar),
+//                              microflux (eq. flux) and phi^{n+1} (eq. phiupdate)
 //
-// Tile kernels: one thread per cell of a 256-cell tile; the thread loops over
-// its slice of discrete velocities, so the velocity sums of face_sums are
-// serial per thread (no atomics, fixed order).  For each velocity the tile and
-// its halo of phi_bar_plus and of the limited slopes are staged in LDS.
+// Face sums: one thread per cell of a 256-cell tile; the thread loops over
+// its slice of discrete velocities, so the velocity sums are serial per
+// thread (no atomics, fixed order).  For each velocity the tile and its halo
+// of phi_bar_plus and of the limited slopes are staged in LDS.  The face
+// values phi_bar (velocity-major [d][g|b][V][NE]) are written once and read
+// by the update, which therefore needs no stencil and no halo.
 #include "cdugks_internal.h"
 
 #include <math.h>
@@ -41,11 +44,25 @@ __device__ __forceinline__ int map_coord(int x, int n, int bc) {
     return x < 0 ? 0 : (x >= n ? n - 1 : x);
 }
 
+// Reciprocal to full double precision without the IEEE division sequence:
+// hardware estimate refined by two Newton-Raphson steps (each squares the
+// relative error).  Used where the operand is a nonzero finite sum.
+__device__ __forceinline__ double fast_rcp(double s) {
+    double r = __builtin_amdgcn_rcp(s);
+    double e = fma(-s, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-s, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Van Leer limiter (eq. VanLeer) in the harmonic-mean form: identical to
 // (sgn a + sgn b)|a||b|/(|a|+|b|); zero at extrema and for a flat side.
+// When a b > 0 the sum a + b is nonzero, so the reciprocal is safe; otherwise
+// its value is discarded by the select.
 __device__ __forceinline__ double van_leer(double a, double b) {
     double p = a * b;
-    return p > 0.0 ? (p + p) / (a + b) : 0.0;
+    double v = (p + p) * fast_rcp(a + b);
+    return p > 0.0 ? v : 0.0;
 }
 
 template <typename ST>
@@ -170,28 +187,22 @@ __device__ __forceinline__ int xcd_remap(int lin, int total) {
     return (lin % 8) * per + lin / 8;
 }
 
-// Box geometry of the staged halo for a tile: q box covers tile offsets
-// [-3, T-1+QH], the limited-slope box [-2, T-1+AH].
-template <int D, bool UPD>
+// Box geometry of the staged halo for a face-sum tile: the q box covers tile
+// offsets [-3, T+1], the limited-difference box [-2, T].  (The left face of
+// cell c along d needs the upwind cell c-d or c, its slopes at the upwind
+// cell +-1 along d, and those need q one further out.)
+template <int D>
 struct Geo {
     static constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
-    static constexpr int QH = UPD ? 3 : 2, AH = UPD ? 2 : 1;
-    static constexpr int QX = TX + 3 + QH;
-    static constexpr int QY = D >= 2 ? TY + 3 + QH : 1;
-    static constexpr int QZ = D >= 3 ? TZ + 3 + QH : 1;
-    static constexpr int AX = TX + 2 + AH;
-    static constexpr int AY = D >= 2 ? TY + 2 + AH : 1;
-    static constexpr int AZ = D >= 3 ? TZ + 2 + AH : 1;
+    static constexpr int QX = TX + 5;
+    static constexpr int QY = D >= 2 ? TY + 5 : 1;
+    static constexpr int QZ = D >= 3 ? TZ + 5 : 1;
+    static constexpr int AX = TX + 3;
+    static constexpr int AY = D >= 2 ? TY + 3 : 1;
+    static constexpr int AZ = D >= 3 ? TZ + 3 : 1;
     static constexpr int NQ = QX * QY * QZ;
     static constexpr int NA = AX * AY * AZ;
-    static constexpr int NRQ = (NQ + WG - 1) / WG;   // q points per thread
     static constexpr int NRA = (NA + WG - 1) / WG;   // slope points per thread
-    // face boxes of the update kernel: along d one more face than cells
-    static constexpr int NF0 = (TX + 1) * TY * TZ;
-    static constexpr int NF1 = D >= 2 ? TX * (TY + 1) * TZ : 0;
-    static constexpr int NF2 = D >= 3 ? TX * TY * (TZ + 1) : 0;
-    static constexpr int NFT = NF0 + NF1 + NF2;
-    static constexpr int NRF = (NFT + WG - 1) / WG;
     static constexpr bool CACHE_COEF = (NQ - TX * TY * TZ + WG - 1) / WG + 1 <= 2;
     // offsets of tile coordinate 0 inside the boxes, and box strides
     static constexpr int OQX = 3, OQY = D >= 2 ? 3 : 0, OQZ = D >= 3 ? 3 : 0;
@@ -225,8 +236,13 @@ struct Vel {
     double xi[3], w, hx2, lam[3];
 };
 
+// The velocity table is read-only for the whole launch: reading it through the
+// constant address space makes the per-velocity loads scalar (SMEM), so they
+// neither occupy vector-memory slots nor delay waits on the field loads.
+typedef const __attribute__((address_space(4))) double* const_dptr;
+
 __device__ __forceinline__ Vel load_vel(const double* vel, int i) {
-    const double* v = vel + (long long)i * NVEL;
+    const_dptr v = (const_dptr)(const void*)(vel + (long long)i * NVEL);
     Vel r;
     r.xi[0] = v[0]; r.xi[1] = v[1]; r.xi[2] = v[2];
     r.w = v[VE_W]; r.hx2 = v[VE_HX2];
@@ -282,12 +298,12 @@ __device__ __forceinline__ void face_pair(const double* const* sq, const double*
                                           int qi_l, int ai_l, int qi_r, int ai_r, const Vel& v,
                                           double& vg, double& vb) {
     const double xd = d == 0 ? v.xi[0] : (d == 1 ? v.xi[1] : v.xi[2]);
-    if (xd > 0.0) {
-        vg = face_value<D, GEO>(sq[0], sa[0], d, qi_l, ai_l, 1.0, v);
-        vb = face_value<D, GEO>(sq[1], sa[1], d, qi_l, ai_l, 1.0, v);
-    } else if (xd < 0.0) {
-        vg = face_value<D, GEO>(sq[0], sa[0], d, qi_r, ai_r, -1.0, v);
-        vb = face_value<D, GEO>(sq[1], sa[1], d, qi_r, ai_r, -1.0, v);
+    if (xd != 0.0) {
+        const bool pos = xd > 0.0;
+        const int qi = pos ? qi_l : qi_r, ai = pos ? ai_l : ai_r;
+        const double s = pos ? 1.0 : -1.0;
+        vg = face_value<D, GEO>(sq[0], sa[0], d, qi, ai, s, v);
+        vb = face_value<D, GEO>(sq[1], sa[1], d, qi, ai, s, v);
     } else {
         vg = 0.5 * (face_value<D, GEO>(sq[0], sa[0], d, qi_l, ai_l, 1.0, v) +
                     face_value<D, GEO>(sq[0], sa[0], d, qi_r, ai_r, -1.0, v));
@@ -347,35 +363,33 @@ struct FaceCoef {
     }
 };
 
-template <int D, typename ST, bool UPD>
-struct TileKernel {
-    using G = Geo<D, UPD>;
+// ---------------------------------------------------------------------------
+// face-sum kernel: for every velocity of the slice, phi_bar at the left face
+// of each tile cell along each d (stored for the update kernel), and the
+// velocity sums of the face (serial per thread, fixed order)
+// ---------------------------------------------------------------------------
+template <int D, typename ST>
+struct FaceSumKernel {
+    using G = Geo<D>;
     static constexpr int NT = G::TX * G::TY * G::TZ;
-    // face coefficients staged in LDS once for the whole velocity loop (1-D
-    // and 2-D); the 3-D kernel reads them from memory (LDS is full)
-    static constexpr bool CACHE_FACE = D <= 2;
-    static constexpr int NFC = FaceCoef<D>::NFC;
     // q-box points per thread: slot 0 is the thread's own cell, the other
     // slots cover the halo
     static constexpr int NHALO = G::NQ - NT;
     static constexpr int NSLOT = 1 + (NHALO + WG - 1) / WG;
 
     struct Smem {
-        double q[2][G::NQ];              // phi_bar_plus for g, b
-        double a[2][D * G::NA];          // limited differences for g, b
-        double f[UPD ? 2 * G::NFT : 1];  // face phi (update kernel)
-        double fc[UPD && CACHE_FACE ? NFC * G::NFT : 1];  // face coefficients
+        double q[2][G::NQ];      // phi_bar_plus for g, b
+        double a[2][D * G::NA];  // limited differences for g, b
     };
 
     __device__ static void run(const Problem& P, int tile, int slice, int nslices, Smem& sm) {
         const int tid = threadIdx.x;
         const long long N = P.N;
-        const int* tiles = UPD ? P.tiles2 : P.tiles1;
         int t = tile;
-        const int ox = (t % tiles[0]) * G::TX;
-        t /= tiles[0];
-        const int oy = D >= 2 ? (t % tiles[1]) * G::TY : 0;
-        t /= tiles[1];
+        const int ox = (t % P.tiles1[0]) * G::TX;
+        t /= P.tiles1[0];
+        const int oy = D >= 2 ? (t % P.tiles1[1]) * G::TY : 0;
+        t /= P.tiles1[1];
         const int oz = D >= 3 ? t * G::TZ : 0;
         const int v0 = (int)((long long)P.V * slice / nslices);
         const int v1 = (int)((long long)P.V * (slice + 1) / nslices);
@@ -412,7 +426,7 @@ struct TileKernel {
             }
 #pragma unroll
             for (int k = 0; k < NSLOT; ++k) {
-                srcq[k] = -1;
+                srcq[k] = 0;  // unused slots still load a valid address
                 if (lq[k] < 0) continue;
                 int r = lq[k];
                 int rx = r % G::QX, ry = (r / G::QX) % G::QY, rz = r / (G::QX * G::QY);
@@ -424,103 +438,85 @@ struct TileKernel {
             }
         }
 
-        // own cell
+        // own cell = the left faces this thread reconstructs
         const int tx = tid % G::TX, ty = (tid / G::TX) % G::TY, tz = tid / (G::TX * G::TY);
         const int gx = ox + tx, gy = oy + ty, gz = oz + tz;
+        const long long NE = P.NE;
+        long long fe = -1;  // extended-grid index of the own cell's left faces
+        bool fvalid[D];
+        {
+            int cc[3] = {gx, gy, gz};
+            bool any = false;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                bool ok = true;
+#pragma unroll
+                for (int e = 0; e < D; ++e) ok &= e == d ? cc[e] < P.ne[e] : cc[e] < P.n[e];
+                fvalid[d] = ok;
+                any |= ok;
+            }
+            if (any) fe = cc[0] + (long long)P.ne[0] * (cc[1] + (long long)P.ne[1] * cc[2]);
+        }
 
-        // face-sum accumulators (face_sums)
         constexpr int NS = 2 * D + 3;
-        double acc[UPD ? 1 : D][UPD ? 1 : NS];
-        if constexpr (!UPD) {
+        double acc[D][NS];
 #pragma unroll
-            for (int d = 0; d < D; ++d)
+        for (int d = 0; d < D; ++d)
 #pragma unroll
-                for (int j = 0; j < NS; ++j) acc[d][j] = 0.0;
-        }
-        const bool own_inside = gx < P.n[0] && (D < 2 || gy < P.n[1]) && (D < 3 || gz < P.n[2]);
-        const long long own = own_inside ? gx + (long long)P.n[0] * (gy + (long long)P.n[1] * gz) : 0;
+            for (int j = 0; j < NS; ++j) acc[d][j] = 0.0;
 
-        // update kernel: own-cell coefficients at n and n+1, and the faces this
-        // thread reconstructs (left faces of tile cells [0, T_d] along d)
-        CellCoef k0, k1;
-        int fd[UPD ? G::NRF : 1], fql[UPD ? G::NRF : 1], fal[UPD ? G::NRF : 1];
-        int fqr[UPD ? G::NRF : 1], far_[UPD ? G::NRF : 1];
-        long long fidx[UPD ? G::NRF : 1];
-        double own_g = 0.0, own_b = 0.0, own_geq = 0.0;
-        if constexpr (UPD) {
-            if (own_inside) {
-                k0 = load_coef(P.P_in, N, own);
-                k1 = load_coef(P.P_out, N, own);
-            }
+        // software pipelining: the next velocity's g, b are loaded while the
+        // current one is processed (when the q-box slots fit in registers)
+        constexpr bool PREFETCH = NSLOT <= 2;
+        double pg[NSLOT], pbv[NSLOT];
+        if constexpr (PREFETCH) {
 #pragma unroll
-            for (int k = 0; k < G::NRF; ++k) {
-                int j = tid + k * WG;
-                fidx[k] = -1;
-                fd[k] = 0;
-                fql[k] = fal[k] = fqr[k] = far_[k] = 0;
-                if (j >= G::NFT) continue;
-                int d, fx, fy, fz;
-                int jj = j;
-                if (jj < G::NF0) {
-                    d = 0; fx = jj % (G::TX + 1); fy = (jj / (G::TX + 1)) % G::TY; fz = jj / ((G::TX + 1) * G::TY);
-                } else if (D >= 2 && (jj -= G::NF0) < G::NF1) {
-                    d = 1; fx = jj % G::TX; fy = (jj / G::TX) % (G::TY + 1); fz = jj / (G::TX * (G::TY + 1));
-                } else {
-                    if (D >= 2) jj -= G::NF1;
-                    d = 2; fx = jj % G::TX; fy = (jj / G::TX) % G::TY; fz = jj / (G::TX * G::TY);
-                }
-                int dxo = d == 0, dyo = d == 1, dzo = d == 2;
-                int cc[3] = {ox + fx, oy + fy, oz + fz};
-                bool valid = true;
-#pragma unroll
-                for (int e = 0; e < D; ++e) {
-                    if (e == d) {
-                        if (cc[e] > P.n[e]) valid = false;
-                        else if (cc[e] == P.n[e] && P.bc[e] == 0) cc[e] = 0;
-                    } else if (cc[e] >= P.n[e]) {
-                        valid = false;
-                    }
-                }
-                fd[k] = d;
-                fql[k] = G::qidx(fx - dxo, fy - dyo, fz - dzo);
-                fal[k] = G::aidx(fx - dxo, fy - dyo, fz - dzo);
-                fqr[k] = G::qidx(fx, fy, fz);
-                far_[k] = G::aidx(fx, fy, fz);
-                if (valid) fidx[k] = cc[0] + (long long)P.ne[0] * (cc[1] + (long long)P.ne[1] * cc[2]);
-                if constexpr (CACHE_FACE) {
-                    FaceCoef<D> fcv{};
-                    if (valid) fcv.load(P.FP + (long long)d * NFP * P.NE + fidx[k], P.NE);
-                    fcv.store(sm.fc, j, G::NFT);
-                }
+            for (int k = 0; k < NSLOT; ++k) {
+                const long long a0 = (long long)(v0 < v1 ? v0 : 0) * N + srcq[k];
+                pg[k] = ld<ST>(P.g_in, a0);
+                pbv[k] = ld<ST>(P.b_in, a0);
             }
-            if constexpr (CACHE_FACE) __syncthreads();
         }
-
+        const long long fstride = (long long)P.V * NE;  // per (d, field) block of FV
         for (int i = v0; i < v1; ++i) {
             const Vel v = load_vel(P.vel, i);
             const long long vb = (long long)i * N;
+            double cg[NSLOT], cbv[NSLOT];
+            if constexpr (PREFETCH) {
+                // unconditional loads (the last velocity re-reads itself) keep
+                // the wait counts exact
+                const long long nb = i + 1 < v1 ? vb + N : vb;
+#pragma unroll
+                for (int k = 0; k < NSLOT; ++k) {
+                    cg[k] = pg[k];
+                    cbv[k] = pbv[k];
+                    pg[k] = ld<ST>(P.g_in, nb + srcq[k]);
+                    pbv[k] = ld<ST>(P.b_in, nb + srcq[k]);
+                }
+            }
 
             // stage 1: quarter-step fields on the q box
 #pragma unroll
             for (int k = 0; k < NSLOT; ++k) {
                 const int r = lq[k];
                 if (r >= 0) {
-                    double g = ld<ST>(P.g_in, vb + srcq[k]);
-                    double b = ld<ST>(P.b_in, vb + srcq[k]);
-                    double qg, qb, geq;
+                    double g, b;
+                    if constexpr (PREFETCH) {
+                        g = cg[k];
+                        b = cbv[k];
+                    } else {
+                        g = ld<ST>(P.g_in, vb + srcq[k]);
+                        b = ld<ST>(P.b_in, vb + srcq[k]);
+                    }
+                    double qg, qb;
                     if constexpr (G::CACHE_COEF) {
-                        geq = quarter_step<D>(kq[k], v, g, b, qg, qb);
+                        quarter_step<D>(kq[k], v, g, b, qg, qb);
                     } else {
                         CellCoef kk = load_coef(P.P_in, N, srcq[k]);
-                        geq = quarter_step<D>(kk, v, g, b, qg, qb);
+                        quarter_step<D>(kk, v, g, b, qg, qb);
                     }
                     sm.q[0][r] = qg;
                     sm.q[1][r] = qb;
-                    if (k == 0) {
-                        own_g = g;
-                        own_b = b;
-                        own_geq = geq;
-                    }
                 }
             }
             __syncthreads();
@@ -546,140 +542,164 @@ struct TileKernel {
             }
             __syncthreads();
 
-            if constexpr (!UPD) {
-                // stage 3: left face of the own cell along each d
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const double xd = v.xi[d];
-                    int dxo = d == 0, dyo = d == 1, dzo = d == 2;
-                    double vg, vb2;
-                    face_pair<D, G>(sqp, sap, d, G::qidx(tx - dxo, ty - dyo, tz - dzo),
-                                    G::aidx(tx - dxo, ty - dyo, tz - dzo), G::qidx(tx, ty, tz),
-                                    G::aidx(tx, ty, tz), v, vg, vb2);
-                    const double wg = v.w * vg, wb = v.w * vb2;
-                    acc[d][0] += wg;
-#pragma unroll
-                    for (int e = 0; e < D; ++e) acc[d][1 + e] += v.xi[e] * wg;
-                    acc[d][D + 1] += wb;
-#pragma unroll
-                    for (int e = 0; e < D; ++e) acc[d][D + 2 + e] += xd * v.xi[e] * wg;
-                    acc[d][2 * D + 2] += xd * wb;
-                }
-                __syncthreads();
-            } else {
-                // stage 3: phi at every face of the tile, inverted with the face
-                // coefficients (eq. phibar)
-#pragma unroll
-                for (int k = 0; k < G::NRF; ++k) {
-                    int j = tid + k * WG;
-                    if (j >= G::NFT) continue;
-                    double gF = 0.0, bF = 0.0;
-                    if (fidx[k] >= 0) {
-                        double vg, vb2;
-                        face_pair<D, G>(sqp, sap, fd[k], fql[k], fal[k], fqr[k], far_[k], v, vg, vb2);
-                        if constexpr (CACHE_FACE) {
-                            FaceCoef<D> f;
-                            f.fetch(sm.fc, j, G::NFT);
-                            f.invert(v, vg, vb2, gF, bF);
-                        } else {
-                            FaceCoef<D> f;
-                            f.load(P.FP + (long long)fd[k] * NFP * P.NE + fidx[k], P.NE);
-                            f.invert(v, vg, vb2, gF, bF);
-                        }
-                    }
-                    sm.f[j] = gF;
-                    sm.f[G::NFT + j] = bF;
-                }
-                __syncthreads();
-
-                // stage 4: microflux and the phi update of the own cell
-                if (own_inside) {
-                    double Fg = 0.0, Fb = 0.0;
-#pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        int jl, jr;
-                        if (d == 0) {
-                            jl = tx + (G::TX + 1) * (ty + G::TY * tz);
-                            jr = jl + 1;
-                        } else if (d == 1) {
-                            jl = G::NF0 + tx + G::TX * (ty + (G::TY + 1) * tz);
-                            jr = jl + G::TX;
-                        } else {
-                            jl = G::NF0 + G::NF1 + tx + G::TX * (ty + G::TY * tz);
-                            jr = jl + G::TX * G::TY;
-                        }
-                        double sxd = v.xi[d] * P.inv_dx[d];
-                        Fg += sxd * (sm.f[jr] - sm.f[jl]);
-                        Fb += sxd * (sm.f[G::NFT + jr] - sm.f[G::NFT + jl]);
-                    }
-                    const double g = own_g, b = own_b, geq0 = own_geq;
-                    double c21 = 0.0, xu0 = 0.0;
-#pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        double x1 = v.xi[d] - k1.u[d];
-                        c21 += x1 * x1;
-                        xu0 += v.xi[d] * k0.u[d];
-                    }
-                    double beq0 = (v.hx2 + k0.cRT2) * geq0;
-                    double geq1 = k1.A * exp(-c21 * k1.inv2RT);
-                    double beq1 = (v.hx2 + k1.cRT2) * geq1;
-                    double Z0 = xu0 - k0.hu2;
-                    const double dt = P.dt;
-                    // eq. phiupdate with dt/(2 tau) = 2 beta and dt S_b = 4 eta Z (g - g_eq)
-                    double gn = (g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg) /
-                                (1.0 + 2.0 * k1.beta);
-                    double bn = (b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
-                                 4.0 * k0.eta * Z0 * (g - geq0)) /
-                                (1.0 + 2.0 * k1.betab);
-                    st<ST>(P.g_out, vb + own, gn);
-                    st<ST>(P.b_out, vb + own, bn);
-                }
-                // q and a are rewritten by the next velocity only after every
-                // thread has passed this velocity's third barrier, the face buffer
-                // after the next velocity's second
-            }
-        }
-
-        if constexpr (!UPD) {
-            // partial face sums of this velocity slice
-            const long long NE = P.NE;
+            // stage 3: left face of the own cell along each d
 #pragma unroll
             for (int d = 0; d < D; ++d) {
-                int cc[3] = {gx, gy, gz};
-                bool valid = true;
-#pragma unroll
-                for (int e = 0; e < D; ++e) {
-                    if (e == d) valid &= cc[e] < P.ne[e];
-                    else valid &= cc[e] < P.n[e];
+                const double xd = v.xi[d];
+                int dxo = d == 0, dyo = d == 1, dzo = d == 2;
+                double vg, vb2;
+                face_pair<D, G>(sqp, sap, d, G::qidx(tx - dxo, ty - dyo, tz - dzo),
+                                G::aidx(tx - dxo, ty - dyo, tz - dzo), G::qidx(tx, ty, tz), G::aidx(tx, ty, tz),
+                                v, vg, vb2);
+                if (fvalid[d]) {
+                    const long long o = (long long)(2 * d) * fstride + (long long)i * NE + fe;
+                    st<ST>(P.FV, o, vg);
+                    st<ST>(P.FV, o + fstride, vb2);
                 }
-                if (!valid) continue;
-                long long fe = cc[0] + (long long)P.ne[0] * (cc[1] + (long long)P.ne[1] * cc[2]);
-                double* out = P.FS + ((long long)(slice * D + d) * NS) * NE + fe;
+                const double wg = v.w * vg, wb = v.w * vb2;
+                acc[d][0] += wg;
 #pragma unroll
-                for (int j = 0; j < NS; ++j) out[(long long)j * NE] = acc[d][j];
+                for (int e = 0; e < D; ++e) acc[d][1 + e] += v.xi[e] * wg;
+                acc[d][D + 1] += wb;
+#pragma unroll
+                for (int e = 0; e < D; ++e) acc[d][D + 2 + e] += xd * v.xi[e] * wg;
+                acc[d][2 * D + 2] += xd * wb;
+            }
+            __syncthreads();
+        }
+
+        // partial face sums of this velocity slice
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            if (!fvalid[d]) continue;
+            double* out = P.FS + ((long long)(slice * D + d) * NS) * NE + fe;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) out[(long long)j * NE] = acc[d][j];
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// update kernel: streaming, one thread per cell over a velocity slice.
+// Reads phi^n and the stored phi_bar at the cell's 2D faces, inverts eq.
+// phibar with the face coefficients, forms the microflux (eq. flux) and writes
+// phi^{n+1} (eq. phiupdate).
+// ---------------------------------------------------------------------------
+template <int D, typename ST>
+struct UpdateKernel {
+    __device__ static void run(const Problem& P, long long c, int slice, int nslices) {
+        const long long N = P.N, NE = P.NE;
+        const bool inside = c < N;
+        const long long cc = inside ? c : 0;
+        int co[3];
+        {
+            long long r = cc;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                co[e] = (int)(r % P.n[e]);
+                r /= P.n[e];
+            }
+        }
+        // left and right faces along each d (periodic wrap at the right end)
+        long long fl[D], fr[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            int rc[3] = {co[0], co[1], co[2]};
+            fl[d] = rc[0] + (long long)P.ne[0] * (rc[1] + (long long)P.ne[1] * rc[2]);
+            rc[d] += 1;
+            if (P.bc[d] == 0 && rc[d] == P.n[d]) rc[d] = 0;
+            fr[d] = rc[0] + (long long)P.ne[0] * (rc[1] + (long long)P.ne[1] * rc[2]);
+        }
+        const CellCoef k0 = load_coef(P.P_in, N, cc);
+        const CellCoef k1 = load_coef(P.P_out, N, cc);
+        FaceCoef<D> fcl[D], fcr[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const double* F = P.FP + (long long)d * NFP * NE;
+            fcl[d].load(F + fl[d], NE);
+            fcr[d].load(F + fr[d], NE);
+        }
+        const int v0 = (int)((long long)P.V * slice / nslices);
+        const int v1 = (int)((long long)P.V * (slice + 1) / nslices);
+        const long long fstride = (long long)P.V * NE;
+        const double dt = P.dt;
+        // constant parts of eq. phiupdate
+        const double inv_g = 1.0 / (1.0 + 2.0 * k1.beta), inv_b = 1.0 / (1.0 + 2.0 * k1.betab);
+
+        for (int i = v0; i < v1; ++i) {
+            const Vel v = load_vel(P.vel, i);
+            const long long vb = (long long)i * N;
+            const double g = ld<ST>(P.g_in, vb + cc);
+            const double b = ld<ST>(P.b_in, vb + cc);
+            double Fg = 0.0, Fb = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const long long o = (long long)(2 * d) * fstride + (long long)i * NE;
+                double gl, bl, gr, br;
+                fcl[d].invert(v, ld<ST>(P.FV, o + fl[d]), ld<ST>(P.FV, o + fstride + fl[d]), gl, bl);
+                fcr[d].invert(v, ld<ST>(P.FV, o + fr[d]), ld<ST>(P.FV, o + fstride + fr[d]), gr, br);
+                const double sxd = v.xi[d] * P.inv_dx[d];
+                Fg += sxd * (gr - gl);
+                Fb += sxd * (br - bl);
+            }
+            double c20 = 0.0, c21 = 0.0, xu0 = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                double x0 = v.xi[d] - k0.u[d], x1 = v.xi[d] - k1.u[d];
+                c20 += x0 * x0;
+                c21 += x1 * x1;
+                xu0 += v.xi[d] * k0.u[d];
+            }
+            const double geq0 = k0.A * exp(-c20 * k0.inv2RT);
+            const double beq0 = (v.hx2 + k0.cRT2) * geq0;
+            const double geq1 = k1.A * exp(-c21 * k1.inv2RT);
+            const double beq1 = (v.hx2 + k1.cRT2) * geq1;
+            const double Z0 = xu0 - k0.hu2;
+            // eq. phiupdate with dt/(2 tau) = 2 beta and dt S_b = 4 eta Z (g - g_eq)
+            const double gn = (g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg) * inv_g;
+            const double bn = (b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
+                               4.0 * k0.eta * Z0 * (g - geq0)) *
+                              inv_b;
+            if (inside) {
+                st<ST>(P.g_out, vb + cc, gn);
+                st<ST>(P.b_out, vb + cc, bn);
             }
         }
     }
 };
 
-template <int D, typename ST, bool UPD>
-__global__ __launch_bounds__(WG) void k_tile(Problem P) {
-    using TK = TileKernel<D, ST, UPD>;
-    __shared__ typename TK::Smem sm;
-    const int* tiles = UPD ? P.tiles2 : P.tiles1;
-    int ntiles = tiles[0] * tiles[1] * tiles[2];
+template <int D, typename ST>
+__global__ __launch_bounds__(WG) void k_face_sums(Problem P) {
+    using K = FaceSumKernel<D, ST>;
+    __shared__ typename K::Smem sm;
+    int ntiles = P.tiles1[0] * P.tiles1[1] * P.tiles1[2];
     int q = xcd_remap(blockIdx.x, gridDim.x);
-    int tile = q % ntiles, slice = q / ntiles;
-    TK::run(P, tile, slice, UPD ? P.nslices_upd : P.nslices, sm);
+    K::run(P, q % ntiles, q / ntiles, P.nslices, sm);
 }
 
-template <int D, typename ST, bool UPD>
-__global__ __launch_bounds__(WG) void k_tile_batched(const Problem* probs, const WorkItem* items) {
-    using TK = TileKernel<D, ST, UPD>;
-    __shared__ typename TK::Smem sm;
+template <int D, typename ST>
+__global__ __launch_bounds__(WG) void k_face_sums_batched(const Problem* probs, const WorkItem* items) {
+    using K = FaceSumKernel<D, ST>;
+    __shared__ typename K::Smem sm;
     const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
     const Problem P = probs[it.prob];
-    TK::run(P, it.tile, it.slice, UPD ? P.nslices_upd : P.nslices, sm);
+    K::run(P, it.tile, it.slice, P.nslices, sm);
+}
+
+// update grid: blocks of 256 consecutive cells x velocity slices
+template <int D, typename ST>
+__global__ __launch_bounds__(WG) void k_update(Problem P) {
+    const int nblk = (int)((P.N + WG - 1) / WG);
+    int q = xcd_remap(blockIdx.x, gridDim.x);
+    int blk = q % nblk, slice = q / nblk;
+    UpdateKernel<D, ST>::run(P, (long long)blk * WG + threadIdx.x, slice, P.nslices_upd);
+}
+
+template <int D, typename ST>
+__global__ __launch_bounds__(WG) void k_update_batched(const Problem* probs, const WorkItem* items) {
+    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
+    const Problem P = probs[it.prob];
+    UpdateKernel<D, ST>::run(P, (long long)it.tile * WG + threadIdx.x, it.slice, P.nslices_upd);
 }
 
 // ---------------------------------------------------------------------------
@@ -902,52 +922,53 @@ hipError_t launch_init(const Problem& P, const double* rho, const double* u, con
     return hipGetLastError();
 }
 
-template <bool UPD>
-static hipError_t launch_tile(const Problem& P, hipStream_t s) {
-    const int* tl = UPD ? P.tiles2 : P.tiles1;
-    unsigned nb = (unsigned)(tl[0] * tl[1] * tl[2] * (UPD ? P.nslices_upd : P.nslices));
-#define CDG_TILE(DD, TT) hipLaunchKernelGGL((k_tile<DD, TT, UPD>), dim3(nb), dim3(WG), 0, s, P)
-    if (P.storage == 0) {
-        if (P.D == 1) CDG_TILE(1, double);
-        else if (P.D == 2) CDG_TILE(2, double);
-        else CDG_TILE(3, double);
-    } else {
-        if (P.D == 1) CDG_TILE(1, float);
-        else if (P.D == 2) CDG_TILE(2, float);
-        else CDG_TILE(3, float);
-    }
-#undef CDG_TILE
+#define CDG_DISPATCH(STORAGE, DIM, MACRO)                            \
+    do {                                                             \
+        if ((STORAGE) == 0) {                                        \
+            if ((DIM) == 1) MACRO(1, double);                        \
+            else if ((DIM) == 2) MACRO(2, double);                   \
+            else MACRO(3, double);                                   \
+        } else {                                                     \
+            if ((DIM) == 1) MACRO(1, float);                         \
+            else if ((DIM) == 2) MACRO(2, float);                    \
+            else MACRO(3, float);                                    \
+        }                                                            \
+    } while (0)
+
+hipError_t launch_face_sums(const Problem& P, hipStream_t s) {
+    unsigned nb = (unsigned)(P.tiles1[0] * P.tiles1[1] * P.tiles1[2] * P.nslices);
+#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT>), dim3(nb), dim3(WG), 0, s, P)
+    CDG_DISPATCH(P.storage, P.D, CDG_L);
+#undef CDG_L
     return hipGetLastError();
 }
 
-template <bool UPD>
-static int blocks_per_cu(int D, int storage) {
+hipError_t launch_update(const Problem& P, hipStream_t s) {
+    unsigned nb = (unsigned)(((P.N + WG - 1) / WG) * P.nslices_upd);
+#define CDG_L(DD, TT) hipLaunchKernelGGL((k_update<DD, TT>), dim3(nb), dim3(WG), 0, s, P)
+    CDG_DISPATCH(P.storage, P.D, CDG_L);
+#undef CDG_L
+    return hipGetLastError();
+}
+
+int tile_blocks_per_cu(int D, int storage, bool update) {
     int n = 0;
-    hipError_t e;
-#define CDG_OCC(DD, TT) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_tile<DD, TT, UPD>), WG, 0)
-    if (storage == 0) {
-        if (D == 1) CDG_OCC(1, double);
-        else if (D == 2) CDG_OCC(2, double);
-        else CDG_OCC(3, double);
+    hipError_t e = hipSuccess;
+    if (update) {
+#define CDG_L(DD, TT) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_update<DD, TT>), WG, 0)
+        CDG_DISPATCH(storage, D, CDG_L);
+#undef CDG_L
     } else {
-        if (D == 1) CDG_OCC(1, float);
-        else if (D == 2) CDG_OCC(2, float);
-        else CDG_OCC(3, float);
+#define CDG_L(DD, TT) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums<DD, TT>), WG, 0)
+        CDG_DISPATCH(storage, D, CDG_L);
+#undef CDG_L
     }
-#undef CDG_OCC
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
     return n;
 }
-
-int tile_blocks_per_cu(int D, int storage, bool update) {
-    return update ? blocks_per_cu<true>(D, storage) : blocks_per_cu<false>(D, storage);
-}
-
-hipError_t launch_face_sums(const Problem& P, hipStream_t s) { return launch_tile<false>(P, s); }
-hipError_t launch_update(const Problem& P, hipStream_t s) { return launch_tile<true>(P, s); }
 
 hipError_t launch_face_close(const Problem& P, hipStream_t s) {
     hipLaunchKernelGGL(k_face_close, dim3(blocks_for(P.NE * P.D)), dim3(WG), 0, s, P);
@@ -974,32 +995,24 @@ hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStre
     return hipGetLastError();
 }
 
-template <bool UPD>
-static hipError_t launch_tile_batched(const Problem* probs, const WorkItem* items, int nitems, int dim,
-                                      int storage, hipStream_t s) {
+hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int dim,
+                                    int storage, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-#define CDG_TILEB(DD, TT) hipLaunchKernelGGL((k_tile_batched<DD, TT, UPD>), dim3(nitems), dim3(WG), 0, s, probs, items)
-    if (storage == 0) {
-        if (dim == 1) CDG_TILEB(1, double);
-        else if (dim == 2) CDG_TILEB(2, double);
-        else CDG_TILEB(3, double);
-    } else {
-        if (dim == 1) CDG_TILEB(1, float);
-        else if (dim == 2) CDG_TILEB(2, float);
-        else CDG_TILEB(3, float);
-    }
-#undef CDG_TILEB
+#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums_batched<DD, TT>), dim3(nitems), dim3(WG), 0, s, probs, items)
+    CDG_DISPATCH(storage, dim, CDG_L);
+#undef CDG_L
     return hipGetLastError();
 }
 
-hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int dim,
-                                    int storage, hipStream_t s) {
-    return launch_tile_batched<false>(probs, items, nitems, dim, storage, s);
-}
 hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, int nitems, int dim,
                                  int storage, hipStream_t s) {
-    return launch_tile_batched<true>(probs, items, nitems, dim, storage, s);
+    if (nitems <= 0) return hipSuccess;
+#define CDG_L(DD, TT) hipLaunchKernelGGL((k_update_batched<DD, TT>), dim3(nitems), dim3(WG), 0, s, probs, items)
+    CDG_DISPATCH(storage, dim, CDG_L);
+#undef CDG_L
+    return hipGetLastError();
 }
+
 hipError_t launch_face_close_batched(const Problem* probs, const long long* offsets, int nprob,
                                      long long total, hipStream_t s) {
     if (total <= 0) return hipSuccess;
