@@ -154,8 +154,10 @@ void cdugks_destroy(cdugks_ctx* ctx);
  * Several independent problems advanced together: each kernel phase of a step
  * is ONE launch over a device work list that covers every tile of every
  * problem, and step sequences are captured as HIP graphs of chunk_steps
- * steps.  Every problem keeps its own context (same stream required) and
- * gets bitwise the same result as when stepped alone. */
+ * steps.  Every problem keeps its own context and gets bitwise the same
+ * result as when stepped alone.  The batch runs on the first context's
+ * stream; work already enqueued on the other members' streams is ordered
+ * before each batch step call and their later work after it. */
 typedef struct cdugks_batch cdugks_batch;
 
 int cdugks_batch_create(cdugks_ctx* const* ctxs, int count, int chunk_steps,
@@ -181,6 +183,16 @@ int cdugks_submit(cdugks_server* srv, const cdugks_space* space, const cdugks_ve
 int cdugks_poll(cdugks_server* srv, uint64_t ticket, double* rho, double* u, double* T,
                 double* t_queue_s, double* t_service_s);
 void cdugks_server_destroy(cdugks_server* srv);
+
+/* ---------------- autotuner ----------------------------------------------
+ * Times candidate launch shapes for the class of this problem (dimension,
+ * storage, velocity count, cell-count bucket): the velocity split of the
+ * update kernel and the persistent grid size of batched launches.  The
+ * fastest is kept in a process-wide table, and written as text to the file
+ * named by $CDUGKS_TUNE_CACHE when that is set (read back at first use).  Every
+ * candidate computes bitwise the same result, so tuning changes speed only.
+ * Advances the context by the steps it times. */
+int cdugks_autotune(cdugks_ctx* ctx, int steps_per_trial);
 
 /* Thread-local message describing the last error on this thread. */
 const char* cdugks_last_error(void);

@@ -14,6 +14,9 @@ ARCH = os.environ.get("CDUGKS_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # contraction only within a source expression: every kernel instantiation
+    # (single problem, batched, any dimension mix) rounds identically
+    "-ffp-contract=on",
     # packed FP32 instructions stay off for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,

@@ -92,6 +92,7 @@ def load_library():
                                          ctypes.POINTER(ctypes.c_uint64)]),
         "cdugks_poll": (ctypes.c_int, [vp, ctypes.c_uint64, _DP, _DP, _DP, _DP, _DP]),
         "cdugks_server_destroy": (None, [vp]),
+        "cdugks_autotune": (ctypes.c_int, [vp, ctypes.c_int]),
         "cdugks_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -209,6 +210,7 @@ class Solver:
     tensor and the stream from torch's current stream."""
 
     def __init__(self, prob: dict, use_torch: bool = False, stream=None):
+        # stream: a hipStream_t handle (ctypes.c_void_p or int) or None
         self.prob = prob
         self.D, self.N, _, _, _ = _fields(prob)
         self.V = int(np.prod([prob["nv"][d] for d in range(self.D)]))
@@ -278,6 +280,80 @@ class Solver:
         check(load_library().cdugks_profile_phases(self.ctx, int(nsteps), _ptr(ms)))
         return ms
 
+    def autotune(self, steps_per_trial: int = 4) -> None:
+        check(load_library().cdugks_autotune(self.ctx, int(steps_per_trial)))
+
     @property
     def dt(self) -> float:
         return self.info()[0]
+
+
+class Batch:
+    """Several Solvers advanced together (one launch per kernel phase for the
+    whole batch, graphs of chunk_steps steps).  All solvers must share a stream."""
+
+    def __init__(self, solvers, chunk_steps: int = 100):
+        self.solvers = list(solvers)
+        arr = (ctypes.c_void_p * len(self.solvers))(*[sv.ctx.value for sv in self.solvers])
+        h = ctypes.c_void_p()
+        check(load_library().cdugks_batch_create(arr, len(self.solvers), int(chunk_steps), ctypes.byref(h)))
+        self.h = h
+
+    def step(self, n: int) -> None:
+        check(load_library().cdugks_batch_step(self.h, int(n)))
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None:
+            load_library().cdugks_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching solve server (host thread inside the library)."""
+
+    def __init__(self, hbm_budget: int, max_active: int = 64, chunk_steps: int = 100, stream=None):
+        h = ctypes.c_void_p()
+        check(load_library().cdugks_server_create(int(hbm_budget), int(max_active), int(chunk_steps), stream,
+                                                  ctypes.byref(h)))
+        self.h = h
+        self._shapes = {}
+
+    def submit(self, prob: dict, nsteps: int) -> int:
+        sp, ve, pa = describe(prob)
+        D, N, rho, u, T = _fields(prob)
+        t = ctypes.c_uint64()
+        check(load_library().cdugks_submit(self.h, ctypes.byref(sp), ctypes.byref(ve), ctypes.byref(pa), _ptr(rho),
+                                           _ptr(u), _ptr(T), int(nsteps), ctypes.byref(t)))
+        self._shapes[t.value] = (D, N)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending; else (rho, u, T, t_queue_s, t_service_s).  Raises
+        CdugksError if the request failed."""
+        D, N = self._shapes[ticket]
+        rho, u, T = np.zeros(N), np.zeros(D * N), np.zeros(N)
+        tq, ts = ctypes.c_double(), ctypes.c_double()
+        rc = load_library().cdugks_poll(self.h, ctypes.c_uint64(ticket), _ptr(rho), _ptr(u), _ptr(T),
+                                        ctypes.byref(tq), ctypes.byref(ts))
+        if rc == PENDING:
+            return None
+        del self._shapes[ticket]
+        check(rc)
+        return rho, u.reshape(D, N), T, tq.value, ts.value
+
+    def close(self) -> None:
+        if getattr(self, "h", None) is not None:
+            load_library().cdugks_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -166,6 +166,9 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
     r.nslices = (int)std::max(1LL, s1);
     long long s2 = plan(nt2, R2);
     r.nslices_upd = (int)std::max(1LL, std::min<long long>(s2, r.V));
+    // the autotuner may have picked another update split for this class
+    // (speed only: the update's result does not depend on it)
+    if (int tu = tuned_update_slices(r); tu > 0) r.nslices_upd = (int)std::min<long long>(tu, r.V);
 
     // byte plan
     const size_t es = r.storage == CDUGKS_STORE_F64 ? 8 : 4;

@@ -41,6 +41,7 @@ void velocity_tables(const Resolved& r, std::vector<double>& vel, std::vector<do
 void fill_problem(const Resolved& r, char* base, Problem& P);
 void set_pingpong(Problem& P, const Resolved& r, char* base, int cur);
 hipError_t enqueue_step(const Problem& P, hipStream_t s);
+int tuned_update_slices(const Resolved& r);
 
 }  // namespace cdg
 

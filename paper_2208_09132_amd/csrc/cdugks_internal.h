@@ -81,14 +81,16 @@ hipError_t launch_moments(const Problem& P, const double* W, double* rho, double
                           hipStream_t s);
 hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStream_t s);
 
-// Batched: one launch per phase across problems.  `items` lists the work of
-// the tile kernels (face sums / update); `cells` and `faces` are prefix offsets
-// (in threads) for the per-cell and per-face kernels; dims counts problems per
-// spatial dimension so that each launch runs one kernel instantiation.
-hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems,
-                                    int dim, int storage, hipStream_t s);
-hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, int nitems,
-                                 int dim, int storage, hipStream_t s);
+// Batched: one launch per phase across problems of one storage class.  The
+// tile-kernel launches are persistent (grid = resident slots, each workgroup
+// strides over the work list); maxd is the largest dimension in the class.
+// The per-face and per-cell closures take per-problem prefix offsets (in
+// threads).
+hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int grid,
+                                    int maxd, int storage, hipStream_t s);
+hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, int nitems, int grid, int maxd,
+                                 int storage, hipStream_t s);
+int batched_blocks_per_cu(int maxd, int storage, bool update);
 hipError_t launch_face_close_batched(const Problem* probs, const long long* offsets, int nprob,
                                      long long total, hipStream_t s);
 hipError_t launch_cell_close_batched(const Problem* probs, const long long* offsets, int nprob,

@@ -677,13 +677,27 @@ __global__ __launch_bounds__(WG) void k_face_sums(Problem P) {
     K::run(P, q % ntiles, q / ntiles, P.nslices, sm);
 }
 
-template <int D, typename ST>
-__global__ __launch_bounds__(WG) void k_face_sums_batched(const Problem* probs, const WorkItem* items) {
-    using K = FaceSumKernel<D, ST>;
-    __shared__ typename K::Smem sm;
-    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
-    const Problem P = probs[it.prob];
-    K::run(P, it.tile, it.slice, P.nslices, sm);
+// Batched face sums: one launch for every tile of every problem of a storage
+// class.  Persistent: the grid covers the resident slots and each workgroup
+// walks the (cost-sorted) work list with a fixed stride, so the assignment of
+// work to workgroups never depends on timing.  Problems of different
+// dimension share the launch; LDS is the union of their needs.
+template <typename ST, int MAXD>
+__global__ __launch_bounds__(WG) void k_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems) {
+    __shared__ union U {
+        typename FaceSumKernel<1, ST>::Smem s1;
+        typename FaceSumKernel<MAXD >= 2 ? 2 : 1, ST>::Smem s2;
+        typename FaceSumKernel<MAXD >= 3 ? 3 : 1, ST>::Smem s3;
+    } sm;
+    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+        const WorkItem it = items[w];
+        const Problem P = probs[it.prob];
+        if (P.D == 1) FaceSumKernel<1, ST>::run(P, it.tile, it.slice, P.nslices, sm.s1);
+        else if (MAXD >= 2 && P.D == 2)
+            FaceSumKernel<MAXD >= 2 ? 2 : 1, ST>::run(P, it.tile, it.slice, P.nslices, sm.s2);
+        else if (MAXD >= 3)
+            FaceSumKernel<MAXD >= 3 ? 3 : 1, ST>::run(P, it.tile, it.slice, P.nslices, sm.s3);
+    }
 }
 
 // update grid: blocks of 256 consecutive cells x velocity slices
@@ -695,11 +709,16 @@ __global__ __launch_bounds__(WG) void k_update(Problem P) {
     UpdateKernel<D, ST>::run(P, (long long)blk * WG + threadIdx.x, slice, P.nslices_upd);
 }
 
-template <int D, typename ST>
-__global__ __launch_bounds__(WG) void k_update_batched(const Problem* probs, const WorkItem* items) {
-    const WorkItem it = items[xcd_remap(blockIdx.x, gridDim.x)];
-    const Problem P = probs[it.prob];
-    UpdateKernel<D, ST>::run(P, (long long)it.tile * WG + threadIdx.x, it.slice, P.nslices_upd);
+template <typename ST, int MAXD>
+__global__ __launch_bounds__(WG) void k_update_batched(const Problem* probs, const WorkItem* items, int nitems) {
+    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+        const WorkItem it = items[w];
+        const Problem P = probs[it.prob];
+        const long long c = (long long)it.tile * WG + threadIdx.x;
+        if (P.D == 1) UpdateKernel<1, ST>::run(P, c, it.slice, P.nslices_upd);
+        else if (MAXD >= 2 && P.D == 2) UpdateKernel<MAXD >= 2 ? 2 : 1, ST>::run(P, c, it.slice, P.nslices_upd);
+        else if (MAXD >= 3) UpdateKernel<MAXD >= 3 ? 3 : 1, ST>::run(P, c, it.slice, P.nslices_upd);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -995,22 +1014,54 @@ hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int dim,
-                                    int storage, hipStream_t s) {
+#define CDG_DISPATCH_MAXD(STORAGE, MAXD, MACRO)                      \
+    do {                                                             \
+        if ((STORAGE) == 0) {                                        \
+            if ((MAXD) == 1) MACRO(double, 1);                       \
+            else if ((MAXD) == 2) MACRO(double, 2);                  \
+            else MACRO(double, 3);                                   \
+        } else {                                                     \
+            if ((MAXD) == 1) MACRO(float, 1);                        \
+            else if ((MAXD) == 2) MACRO(float, 2);                   \
+            else MACRO(float, 3);                                    \
+        }                                                            \
+    } while (0)
+
+hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int grid,
+                                    int maxd, int storage, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums_batched<DD, TT>), dim3(nitems), dim3(WG), 0, s, probs, items)
-    CDG_DISPATCH(storage, dim, CDG_L);
+#define CDG_L(TT, MD) hipLaunchKernelGGL((k_face_sums_batched<TT, MD>), dim3(grid), dim3(WG), 0, s, probs, items, nitems)
+    CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
 #undef CDG_L
     return hipGetLastError();
 }
 
-hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, int nitems, int dim,
+hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, int nitems, int grid, int maxd,
                                  int storage, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-#define CDG_L(DD, TT) hipLaunchKernelGGL((k_update_batched<DD, TT>), dim3(nitems), dim3(WG), 0, s, probs, items)
-    CDG_DISPATCH(storage, dim, CDG_L);
+#define CDG_L(TT, MD) hipLaunchKernelGGL((k_update_batched<TT, MD>), dim3(grid), dim3(WG), 0, s, probs, items, nitems)
+    CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
 #undef CDG_L
     return hipGetLastError();
+}
+
+int batched_blocks_per_cu(int maxd, int storage, bool update) {
+    int n = 0;
+    hipError_t e = hipSuccess;
+    if (update) {
+#define CDG_L(TT, MD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_update_batched<TT, MD>), WG, 0)
+        CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
+#undef CDG_L
+    } else {
+#define CDG_L(TT, MD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums_batched<TT, MD>), WG, 0)
+        CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
+#undef CDG_L
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
 }
 
 hipError_t launch_face_close_batched(const Problem* probs, const long long* offsets, int nprob,

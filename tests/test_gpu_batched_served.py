@@ -1,0 +1,144 @@
+"""GPU tests of the batched and served forms: every problem gives bitwise the
+same result alone and in a mix; a sampled problem matches the oracle; the
+server admits by memory budget and isolates failures."""
+import ctypes
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_2208_09132_amd import cdugks as cd
+from paper_2208_09132_amd import workloads as wl
+from tests.helpers import make_oracle, moment_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def mixed_problems(seed=77, count=6):
+    rng = wl.SplitMix64(seed)
+    probs = []
+    for k in range(count):
+        if k % 2 == 0:
+            p = wl.random_fourier(1, [rng.integer(40, 300)], [rng.integer(8, 33)], rng, Kn=10 ** rng.uniform(-3, 0),
+                                  Pr=[0.5, 2.0 / 3.0, 1.0, 2.0][k % 4])
+        else:
+            n, m = rng.integer(12, 40), rng.integer(6, 12)
+            p = wl.random_fourier(2, [n, n], [m, m], rng, Kn=10 ** rng.uniform(-3, 0), Pr=[2.0, 1.0, 0.5][k % 3])
+        p["storage"] = "f32" if k % 3 == 1 else "f64"
+        probs.append(p)
+    return probs
+
+
+def alone(prob, steps):
+    s = cd.Solver(prob)
+    s.step(steps)
+    m = s.moments()
+    s.close()
+    return m
+
+
+def test_batched_equals_alone_bitwise():
+    probs = mixed_problems()
+    steps = 13  # one 10-step graph chunk + an odd remainder
+    ref = [alone(p, steps) for p in probs]
+    solvers = [cd.Solver(p) for p in probs]
+    b = cd.Batch(solvers, chunk_steps=10)
+    b.step(steps)
+    b.close()
+    for k, (s, r) in enumerate(zip(solvers, ref)):
+        got = s.moments()
+        for a, c in zip(got, r):
+            assert np.array_equal(a, c), f"problem {k} differs: {moment_errors(r, got)}"
+        s.close()
+    _log(f"batched: {len(probs)} problems bitwise equal to their solo runs")
+
+
+def test_batched_sample_matches_oracle():
+    probs = mixed_problems(seed=5, count=4)
+    solvers = [cd.Solver(p) for p in probs]
+    b = cd.Batch(solvers, chunk_steps=4)
+    b.step(8)
+    b.close()
+    for p, s in zip(probs, solvers):
+        got = s.moments()
+        o = make_oracle(p, dt=s.dt)
+        assert o.step(8) == 0
+        errs = moment_errors(o.moments(), got)
+        tol = 1e-12 if p["storage"] == "f64" else 1e-5
+        _log(f"batched vs oracle: dim={p['dim']} storage={p['storage']} errs={errs}")
+        assert max(errs) <= tol
+        s.close()
+
+
+def test_autotune_keeps_results():
+    p = wl.kelvin_helmholtz(n=48, nv=10)
+    a = cd.Solver(p)
+    a.step(6)
+    ref = a.moments()
+    a.close()
+    t = cd.Solver(p)
+    t.autotune(2)  # advances by its trial steps
+    t.close()
+    c = cd.Solver(p)  # picks the tuned split for this class
+    c.step(6)
+    got = c.moments()
+    c.close()
+    for x, y in zip(ref, got):
+        assert np.array_equal(x, y)
+
+
+def test_server_results_equal_alone_and_budget_admission():
+    probs = mixed_problems(seed=31, count=5)
+    steps = [7, 12, 5, 9, 11]
+    ref = [alone(p, n) for p, n in zip(probs, steps)]
+    need = [cd.cdugks_required_bytes(p) for p in probs]
+    budget = int(max(need) * 2.2)  # forces queueing: at most two or three at once
+    srv = cd.Server(budget, max_active=3, chunk_steps=4)
+    tickets = [srv.submit(p, n) for p, n in zip(probs, steps)]
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets) and time.time() - t0 < 60:
+        for t in tickets:
+            if t not in done:
+                r = srv.poll(t)
+                if r is not None:
+                    done[t] = r
+        time.sleep(0.005)
+    assert len(done) == len(tickets)
+    for t, r in zip(tickets, ref):
+        rho, u, T, tq, ts = done[t]
+        assert np.array_equal(rho, r[0]) and np.array_equal(u, r[1]) and np.array_equal(T, r[2])
+        assert tq >= 0 and ts > 0
+    # a request larger than the whole budget is refused up front
+    big = wl.kelvin_helmholtz(n=128, nv=20)
+    with pytest.raises(cd.CdugksError) as ei:
+        srv.submit(big, 1)
+    assert ei.value.code == cd.ERR_TOO_LARGE
+    srv.close()
+
+
+def test_server_isolates_a_failing_request():
+    good = mixed_problems(seed=9, count=3)
+    bad = dict(good[0])
+    bad["rho"] = good[0]["rho"].copy()
+    bad["rho"][2] = -1.0  # rejected when the server initialises it
+    srv = cd.Server(1 << 34, max_active=4, chunk_steps=3)
+    tg = [srv.submit(p, 5) for p in good]
+    with pytest.raises(cd.CdugksError):
+        # the host validation already refuses it at submit time
+        srv.submit(bad, 5)
+    for t, p in zip(tg, good):
+        r = None
+        t0 = time.time()
+        while r is None and time.time() - t0 < 30:
+            r = srv.poll(t)
+            time.sleep(0.002)
+        ref = alone(p, 5)
+        assert np.array_equal(r[0], ref[0])
+    srv.close()
