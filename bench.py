@@ -61,6 +61,91 @@ def time_gpu(prob, steps: int, warmup: int):
     return N, V, wall, phase_ms
 
 
+def copy_ceiling(nbytes: int = 1 << 32):
+    """Device-to-device copy bandwidth (read + write bytes / time): the
+    practical HBM ceiling next to the 8 TB/s published peak."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def batched_run(count: int, chunk: int, warm_chunks: int = 1, timed_chunks: int = 1):
+    """The uneven batch (1D and 2D random-Fourier problems, FP32), advanced as
+    one batch: persistent launches per phase, HIP-graph chunks."""
+    from paper_2208_09132_amd import cdugks as cd
+    from paper_2208_09132_amd import workloads as wl
+
+    probs = wl.batched(count=count)
+    solvers = [cd.Solver(p) for p in probs]
+    updates = sum(s.N * s.V for s in solvers)
+    b = cd.Batch(solvers, chunk_steps=chunk)
+    b.step(chunk * warm_chunks)
+    for s in solvers:
+        s.sync()
+    t0 = time.perf_counter()
+    b.step(chunk * timed_chunks)
+    solvers[0].sync()
+    wall = time.perf_counter() - t0
+    b.close()
+    for s in solvers:
+        s.close()
+    steps = chunk * timed_chunks
+    return {"value": updates * steps / wall, "unit": "updates/s", "problems": count, "steps": steps,
+            "updates_per_step": updates, "ms_per_step": 1e3 * wall / steps, "storage": "f32",
+            "dims": {"1d": sum(p["dim"] == 1 for p in probs), "2d": sum(p["dim"] == 2 for p in probs)}}
+
+
+def served_run(nreq: int, budget_gb: float = 200.0, max_active: int = 64, chunk: int = 100):
+    """A prefix of the seeded Poisson stream (lambda = 50/s) submitted at its
+    arrival times to the continuous-batching server."""
+    from paper_2208_09132_amd import cdugks as cd
+    from paper_2208_09132_amd import workloads as wl
+
+    stream = wl.served_stream()[:nreq]
+    srv = cd.Server(int(budget_gb * 1e9), max_active=max_active, chunk_steps=chunk)
+    t0 = time.perf_counter()
+    tickets, upd = [], 0
+    for arrival, p in stream:
+        while time.perf_counter() - t0 < arrival:
+            time.sleep(min(0.001, max(0.0, arrival - (time.perf_counter() - t0))))
+        tickets.append((srv.submit(p, p["steps"]), p))
+        upd += int(np.prod(p["n"])) * int(np.prod(p["nv"])) * p["steps"]
+    lat, qs, ss = [], [], []
+    pending = dict(tickets)
+    while pending:
+        for t in list(pending):
+            r = srv.poll(t)
+            if r is not None:
+                _, _, _, tq, ts = r
+                qs.append(tq)
+                ss.append(ts)
+                lat.append(tq + ts)
+                del pending[t]
+        time.sleep(0.002)
+    makespan = time.perf_counter() - t0
+    srv.close()
+    pct = lambda a, q: float(np.percentile(np.array(a), q))
+    span = stream[-1][0] if stream else 0.0
+    return {"requests": nreq, "throughput": upd / makespan, "unit": "updates/s", "makespan_s": makespan,
+            "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99),
+            "p50_queue_s": pct(qs, 50), "p99_queue_s": pct(qs, 99),
+            "p50_service_s": pct(ss, 50), "p99_service_s": pct(ss, 99),
+            "offered_updates_per_s": upd / span if span > 0 else None,
+            "arrival_rate_per_s": 50.0, "budget_gb": budget_gb, "storage": "f32"}
+
+
 def cpu_baseline(prob, budget_s: float = 20.0):
     """The FP64 oracle on the host cores: one step of the same workload (a
     smaller tile of cells when one full step would exceed the budget)."""
@@ -87,6 +172,8 @@ def main():
     ap.add_argument("--config", default="kh")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--batched-problems", type=int, default=256)
+    ap.add_argument("--served-requests", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design note, "
@@ -127,6 +214,13 @@ def main():
                              "speedup_vs_fp64": ups32 / ups,
                              "phase_ms": {k: float(v) for k, v in zip(PHASES, ph2)},
                              "step_algorithmic_frac": ALGO_BYTES["f32"] * ups32 / 1e9 / HBM_PEAK_GBS}
+    if args.batched_problems > 0:
+        out["batched"] = batched_run(args.batched_problems, chunk=100)
+        out["batched"]["speedup_vs_fp64_plain"] = out["batched"]["value"] / ups
+    if args.served_requests > 0:
+        out["served"] = served_run(args.served_requests)
+    out["copy_ceiling_GBps"] = copy_ceiling()
+    out["roofline"]["frac_of_copy_ceiling"] = achieved / out["copy_ceiling_GBps"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
