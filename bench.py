@@ -62,17 +62,18 @@ def time_gpu(prob, steps: int, warmup: int):
 
 
 def copy_ceiling(nbytes: int = 1 << 32):
-    """Device-to-device copy bandwidth (read + write bytes / time): the
-    practical HBM ceiling next to the 8 TB/s published peak."""
+    """Streaming bandwidth of a plain elementwise kernel (y = 1 * x over 4 GiB;
+    read + write bytes / time): the practical HBM ceiling next to the 8 TB/s
+    published peak."""
     import torch
-    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
-    y.copy_(x)
+    torch.mul(x, 1.0, out=y)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(5):
-        y.copy_(x)
+        torch.mul(x, 1.0, out=y)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / 5

@@ -160,12 +160,13 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
         long long s = (R + ntiles / 2) / ntiles;
         return std::max(1LL, s);
     };
+    // at least 16 velocities per slice so the per-tile set-up stays amortised
+    const long long smax = std::max(1LL, r.V / 16);
     int slices = pa->velocity_slices;
-    long long s1 = slices > 0 ? slices : plan(nt1, R1);
-    s1 = std::min<long long>(s1, std::max(1LL, r.V / 2));
+    long long s1 = slices > 0 ? std::min<long long>(slices, r.V) : std::min(plan(nt1, R1), smax);
     r.nslices = (int)std::max(1LL, s1);
-    long long s2 = plan(nt2, R2);
-    r.nslices_upd = (int)std::max(1LL, std::min<long long>(s2, r.V));
+    long long s2 = std::min(plan(nt2, R2), smax);
+    r.nslices_upd = (int)std::max(1LL, s2);
     // the autotuner may have picked another update split for this class
     // (speed only: the update's result does not depend on it)
     if (int tu = tuned_update_slices(r); tu > 0) r.nslices_upd = (int)std::min<long long>(tu, r.V);

@@ -65,6 +65,17 @@ __device__ __forceinline__ double van_leer(double a, double b) {
     return p > 0.0 ? v : 0.0;
 }
 
+// FP32 form of the limiter for the FP32-storage stencil: the hardware
+// reciprocal plus one Newton step.
+__device__ __forceinline__ float van_leer(float a, float b) {
+    float p = a * b;
+    float s = a + b;
+    float r = __builtin_amdgcn_rcpf(s);
+    r = fmaf(r, fmaf(-s, r, 1.0f), r);
+    float v = (p + p) * r;
+    return p > 0.0f ? v : 0.0f;
+}
+
 template <typename ST>
 __device__ __forceinline__ double ld(const void* base, long long idx) {
     return (double)reinterpret_cast<const ST*>(base)[idx];
@@ -72,6 +83,14 @@ __device__ __forceinline__ double ld(const void* base, long long idx) {
 template <typename ST>
 __device__ __forceinline__ void st(void* base, long long idx, double v) {
     reinterpret_cast<ST*>(base)[idx] = (ST)v;
+}
+
+// Streaming store for data the writing kernel never reads again (face values,
+// the new distributions): marked non-temporal so it does not push the halo
+// lines that neighbouring workgroups still need out of L2.
+template <typename ST>
+__device__ __forceinline__ void st_stream(void* base, long long idx, double v) {
+    __builtin_nontemporal_store((ST)v, reinterpret_cast<ST*>(base) + idx);
 }
 
 __device__ __forceinline__ void raise_error(int* err) { *err = 1; }
@@ -276,39 +295,40 @@ __device__ __forceinline__ double quarter_step(const CellCoef& k, const Vel& v, 
 //   v = q(u) + s a_d/2 - sum_e lambda_e (a_e + s b_de/2),
 // a_e = VL of one-sided differences of q along e (slope times dx_e) and
 // b_de = VL of differences of a_e along d (slope of the slope times dx_d dx_e).
-template <int D, class GEO>
-__device__ __forceinline__ double face_value(const double* sq, const double* sa, int d, int qi,
-                                             int ai, double s, const Vel& v) {
+template <int D, class GEO, typename CT>
+__device__ __forceinline__ CT face_value(const CT* sq, const CT* sa, int d, int qi, int ai, CT s,
+                                         const Vel& v) {
     const int sd = GEO::SA(d);
-    double val = sq[qi] + 0.5 * s * sa[d * GEO::NA + ai];
+    const CT half = CT(0.5);
+    CT val = sq[qi] + half * s * sa[d * GEO::NA + ai];
 #pragma unroll
     for (int e = 0; e < D; ++e) {
-        const double* ae = sa + e * GEO::NA;
-        double a0 = ae[ai];
-        double bde = van_leer(a0 - ae[ai - sd], ae[ai + sd] - a0);
-        val -= v.lam[e] * (a0 + 0.5 * s * bde);
+        const CT* ae = sa + e * GEO::NA;
+        CT a0 = ae[ai];
+        CT bde = van_leer(a0 - ae[ai - sd], ae[ai + sd] - a0);
+        val -= CT(v.lam[e]) * (a0 + half * s * bde);
     }
     return val;
 }
 
 // Both one-sided candidates of a face: left upwind cell (qi_l, ai_l) used when
 // xi_d > 0, right upwind cell (qi_r, ai_r) when xi_d < 0, their mean at xi_d = 0.
-template <int D, class GEO>
-__device__ __forceinline__ void face_pair(const double* const* sq, const double* const* sa, int d,
-                                          int qi_l, int ai_l, int qi_r, int ai_r, const Vel& v,
-                                          double& vg, double& vb) {
+template <int D, class GEO, typename CT>
+__device__ __forceinline__ void face_pair(const CT* const* sq, const CT* const* sa, int d, int qi_l, int ai_l,
+                                          int qi_r, int ai_r, const Vel& v, CT& vg, CT& vb) {
     const double xd = d == 0 ? v.xi[0] : (d == 1 ? v.xi[1] : v.xi[2]);
     if (xd != 0.0) {
         const bool pos = xd > 0.0;
         const int qi = pos ? qi_l : qi_r, ai = pos ? ai_l : ai_r;
-        const double s = pos ? 1.0 : -1.0;
-        vg = face_value<D, GEO>(sq[0], sa[0], d, qi, ai, s, v);
-        vb = face_value<D, GEO>(sq[1], sa[1], d, qi, ai, s, v);
+        const CT s = pos ? CT(1) : CT(-1);
+        vg = face_value<D, GEO, CT>(sq[0], sa[0], d, qi, ai, s, v);
+        vb = face_value<D, GEO, CT>(sq[1], sa[1], d, qi, ai, s, v);
     } else {
-        vg = 0.5 * (face_value<D, GEO>(sq[0], sa[0], d, qi_l, ai_l, 1.0, v) +
-                    face_value<D, GEO>(sq[0], sa[0], d, qi_r, ai_r, -1.0, v));
-        vb = 0.5 * (face_value<D, GEO>(sq[1], sa[1], d, qi_l, ai_l, 1.0, v) +
-                    face_value<D, GEO>(sq[1], sa[1], d, qi_r, ai_r, -1.0, v));
+        const CT half = CT(0.5);
+        vg = half * (face_value<D, GEO, CT>(sq[0], sa[0], d, qi_l, ai_l, CT(1), v) +
+                     face_value<D, GEO, CT>(sq[0], sa[0], d, qi_r, ai_r, CT(-1), v));
+        vb = half * (face_value<D, GEO, CT>(sq[1], sa[1], d, qi_l, ai_l, CT(1), v) +
+                     face_value<D, GEO, CT>(sq[1], sa[1], d, qi_r, ai_r, CT(-1), v));
     }
 }
 
@@ -371,15 +391,68 @@ struct FaceCoef {
 template <int D, typename ST>
 struct FaceSumKernel {
     using G = Geo<D>;
+    // stencil arithmetic (quarter-step values in LDS, limiters, face values) in
+    // the storage precision; equilibria and the velocity sums stay FP64
+    using CT = ST;
     static constexpr int NT = G::TX * G::TY * G::TZ;
     // q-box points per thread: slot 0 is the thread's own cell, the other
     // slots cover the halo
     static constexpr int NHALO = G::NQ - NT;
     static constexpr int NSLOT = 1 + (NHALO + WG - 1) / WG;
 
+    // Box index of the h-th halo point of the q box in box order (interior
+    // points skipped): planes below the interior in z are full, the interior
+    // planes miss the tile's TX x TY block, and likewise rows within a plane.
+    __device__ static int halo_point(int h) {
+        constexpr int QX = G::QX, QY = G::QY, QZ = G::QZ;
+        constexpr int PL = QX * QY;                 // points per full plane
+        constexpr int PI = PL - G::TX * G::TY;      // halo points per interior plane
+        constexpr int RI = QX - G::TX;              // halo points per interior row
+        int z, rem;
+        if (h < G::OQZ * PL) {
+            z = h / PL;
+            return h;  // below the interior: box order equals halo order
+        }
+        h -= G::OQZ * PL;
+        if (h >= G::TZ * PI) {
+            h -= G::TZ * PI;
+            return (G::OQZ + G::TZ) * PL + h;  // above the interior
+        }
+        z = G::OQZ + h / PI;
+        rem = h % PI;
+        int y, x;
+        if (rem < G::OQY * QX) {
+            y = rem / QX;
+            x = rem % QX;
+        } else {
+            rem -= G::OQY * QX;
+            if (rem >= G::TY * RI) {
+                rem -= G::TY * RI;
+                y = G::OQY + G::TY + rem / QX;
+                x = rem % QX;
+            } else {
+                y = G::OQY + rem / RI;
+                int c = rem % RI;
+                x = c < G::OQX ? c : c + G::TX;
+            }
+        }
+        (void)QZ;
+        return x + QX * (y + QY * z);
+    }
+
+    // when the q-box points do not fit in registers, the cell coefficients
+    // of the whole box are staged in LDS once (3-D FP32; the FP64 3-D box does
+    // not fit and reads them from memory)
+    static constexpr bool COEF_LDS = !G::CACHE_COEF && sizeof(CT) == 4;
+
+    // 1-D and 2-D alternate two LDS buffers between consecutive velocities,
+    // which removes the barrier that would otherwise end each velocity
+    static constexpr int NBUF = D <= 2 ? 2 : 1;
+
     struct Smem {
-        double q[2][G::NQ];      // phi_bar_plus for g, b
-        double a[2][D * G::NA];  // limited differences for g, b
+        CT q[NBUF][2][G::NQ];      // phi_bar_plus for g, b
+        CT a[NBUF][2][D * G::NA];  // limited differences for g, b
+        double kc[COEF_LDS ? 10 * G::NQ : 1];  // [coefficient][box point]
     };
 
     __device__ static void run(const Problem& P, int tile, int slice, int nslices, Smem& sm) {
@@ -393,8 +466,6 @@ struct FaceSumKernel {
         const int oz = D >= 3 ? t * G::TZ : 0;
         const int v0 = (int)((long long)P.V * slice / nslices);
         const int v1 = (int)((long long)P.V * (slice + 1) / nslices);
-        const double* sqp[2] = {sm.q[0], sm.q[1]};
-        const double* sap[2] = {sm.a[0], sm.a[1]};
 
         // q-box points of this thread: slot 0 its own cell, then halo points
         // (halo enumerated in box order, interior skipped); source cell after
@@ -403,26 +474,12 @@ struct FaceSumKernel {
         int lq[NSLOT];
         CellCoef kq[G::CACHE_COEF ? NSLOT : 1];
         {
-            int want[NSLOT];
+            int lx = tid % G::TX, ly = (tid / G::TX) % G::TY, lz = tid / (G::TX * G::TY);
+            lq[0] = G::qidx(lx, ly, lz);
 #pragma unroll
-            for (int k = 0; k < NSLOT; ++k) {
-                lq[k] = -1;
-                want[k] = k == 0 ? -1 : tid + (k - 1) * WG;  // halo ordinal
-            }
-            {
-                int lx = tid % G::TX, ly = (tid / G::TX) % G::TY, lz = tid / (G::TX * G::TY);
-                lq[0] = G::qidx(lx, ly, lz);
-            }
-            int h = 0;
-            for (int r = 0; r < G::NQ; ++r) {
-                int rx = r % G::QX, ry = (r / G::QX) % G::QY, rz = r / (G::QX * G::QY);
-                int lx = rx - G::OQX, ly = ry - G::OQY, lz = rz - G::OQZ;
-                bool interior = lx >= 0 && lx < G::TX && ly >= 0 && ly < G::TY && lz >= 0 && lz < G::TZ;
-                if (interior) continue;
-#pragma unroll
-                for (int k = 1; k < NSLOT; ++k)
-                    if (want[k] == h) lq[k] = r;
-                ++h;
+            for (int k = 1; k < NSLOT; ++k) {
+                const int h = tid + (k - 1) * WG;  // halo ordinal
+                lq[k] = h < NHALO ? halo_point(h) : -1;
             }
 #pragma unroll
             for (int k = 0; k < NSLOT; ++k) {
@@ -436,6 +493,20 @@ struct FaceSumKernel {
                 srcq[k] = cx + (long long)P.n[0] * (cy + (long long)P.n[1] * cz);
                 if constexpr (G::CACHE_COEF) kq[k] = load_coef(P.P_in, N, srcq[k]);
             }
+        }
+        if constexpr (COEF_LDS) {
+            for (int r = tid; r < G::NQ; r += WG) {
+                int rx = r % G::QX, ry = (r / G::QX) % G::QY, rz = r / (G::QX * G::QY);
+                int cx = map_coord(ox + rx - G::OQX, P.n[0], P.bc[0]);
+                int cy = D >= 2 ? map_coord(oy + ry - G::OQY, P.n[1], P.bc[1]) : 0;
+                int cz = D >= 3 ? map_coord(oz + rz - G::OQZ, P.n[2], P.bc[2]) : 0;
+                const CellCoef k = load_coef(P.P_in, N, cx + (long long)P.n[0] * (cy + (long long)P.n[1] * cz));
+                double* o = sm.kc + r;
+                o[0 * G::NQ] = k.A; o[1 * G::NQ] = k.inv2RT; o[2 * G::NQ] = k.cRT2; o[3 * G::NQ] = k.beta;
+                o[4 * G::NQ] = k.betab; o[5 * G::NQ] = k.eta; o[6 * G::NQ] = k.hu2;
+                o[7 * G::NQ] = k.u[0]; o[8 * G::NQ] = k.u[1]; o[9 * G::NQ] = k.u[2];
+            }
+            __syncthreads();
         }
 
         // own cell = the left faces this thread reconstructs
@@ -481,6 +552,13 @@ struct FaceSumKernel {
         for (int i = v0; i < v1; ++i) {
             const Vel v = load_vel(P.vel, i);
             const long long vb = (long long)i * N;
+            const int buf = NBUF == 2 ? ((i - v0) & 1) : 0;
+            CT* const sq0 = sm.q[buf][0];
+            CT* const sq1 = sm.q[buf][1];
+            CT* const sa0 = sm.a[buf][0];
+            CT* const sa1 = sm.a[buf][1];
+            const CT* sqp[2] = {sq0, sq1};
+            const CT* sap[2] = {sa0, sa1};
             double cg[NSLOT], cbv[NSLOT];
             if constexpr (PREFETCH) {
                 // unconditional loads (the last velocity re-reads itself) keep
@@ -511,12 +589,20 @@ struct FaceSumKernel {
                     double qg, qb;
                     if constexpr (G::CACHE_COEF) {
                         quarter_step<D>(kq[k], v, g, b, qg, qb);
+                    } else if constexpr (COEF_LDS) {
+                        const double* o = sm.kc + r;
+                        CellCoef kk;
+                        kk.A = o[0 * G::NQ]; kk.inv2RT = o[1 * G::NQ]; kk.cRT2 = o[2 * G::NQ];
+                        kk.beta = o[3 * G::NQ]; kk.betab = o[4 * G::NQ]; kk.eta = o[5 * G::NQ];
+                        kk.hu2 = o[6 * G::NQ]; kk.u[0] = o[7 * G::NQ]; kk.u[1] = o[8 * G::NQ];
+                        kk.u[2] = o[9 * G::NQ];
+                        quarter_step<D>(kk, v, g, b, qg, qb);
                     } else {
                         CellCoef kk = load_coef(P.P_in, N, srcq[k]);
                         quarter_step<D>(kk, v, g, b, qg, qb);
                     }
-                    sm.q[0][r] = qg;
-                    sm.q[1][r] = qb;
+                    sq0[r] = CT(qg);
+                    sq1[r] = CT(qb);
                 }
             }
             __syncthreads();
@@ -533,9 +619,9 @@ struct FaceSumKernel {
                         int sq = G::SQ(e);
 #pragma unroll
                         for (int f = 0; f < 2; ++f) {
-                            const double* q = sm.q[f];
-                            double c = q[qi];
-                            sm.a[f][e * G::NA + p] = van_leer(c - q[qi - sq], q[qi + sq] - c);
+                            const CT* q = f == 0 ? sq0 : sq1;
+                            CT c = q[qi];
+                            (f == 0 ? sa0 : sa1)[e * G::NA + p] = van_leer(c - q[qi - sq], q[qi + sq] - c);
                         }
                     }
                 }
@@ -547,14 +633,15 @@ struct FaceSumKernel {
             for (int d = 0; d < D; ++d) {
                 const double xd = v.xi[d];
                 int dxo = d == 0, dyo = d == 1, dzo = d == 2;
-                double vg, vb2;
-                face_pair<D, G>(sqp, sap, d, G::qidx(tx - dxo, ty - dyo, tz - dzo),
-                                G::aidx(tx - dxo, ty - dyo, tz - dzo), G::qidx(tx, ty, tz), G::aidx(tx, ty, tz),
-                                v, vg, vb2);
+                CT vgc, vbc;
+                face_pair<D, G, CT>(sqp, sap, d, G::qidx(tx - dxo, ty - dyo, tz - dzo),
+                                    G::aidx(tx - dxo, ty - dyo, tz - dzo), G::qidx(tx, ty, tz),
+                                    G::aidx(tx, ty, tz), v, vgc, vbc);
+                const double vg = vgc, vb2 = vbc;
                 if (fvalid[d]) {
                     const long long o = (long long)(2 * d) * fstride + (long long)i * NE + fe;
-                    st<ST>(P.FV, o, vg);
-                    st<ST>(P.FV, o + fstride, vb2);
+                    st_stream<ST>(P.FV, o, vg);
+                    st_stream<ST>(P.FV, o + fstride, vb2);
                 }
                 const double wg = v.w * vg, wb = v.w * vb2;
                 acc[d][0] += wg;
@@ -565,7 +652,11 @@ struct FaceSumKernel {
                 for (int e = 0; e < D; ++e) acc[d][D + 2 + e] += xd * v.xi[e] * wg;
                 acc[d][2 * D + 2] += xd * wb;
             }
-            __syncthreads();
+            // single-buffered: the next velocity must not overwrite q and a
+            // before every thread has read them; double-buffered: the next
+            // velocity writes the other buffer, and the one after that comes
+            // only after two more barriers
+            if constexpr (NBUF == 1) __syncthreads();
         }
 
         // partial face sums of this velocity slice
@@ -626,6 +717,10 @@ struct UpdateKernel {
         // constant parts of eq. phiupdate
         const double inv_g = 1.0 / (1.0 + 2.0 * k1.beta), inv_b = 1.0 / (1.0 + 2.0 * k1.betab);
 
+        // FP64: two velocities per trip (twice the loads in flight per wave);
+        // FP32 keeps one, which leaves room for a third wave per SIMD
+        constexpr int UNROLL = sizeof(ST) == 8 ? 2 : 1;
+#pragma unroll UNROLL
         for (int i = v0; i < v1; ++i) {
             const Vel v = load_vel(P.vel, i);
             const long long vb = (long long)i * N;
@@ -661,8 +756,8 @@ struct UpdateKernel {
                                4.0 * k0.eta * Z0 * (g - geq0)) *
                               inv_b;
             if (inside) {
-                st<ST>(P.g_out, vb + cc, gn);
-                st<ST>(P.b_out, vb + cc, bn);
+                st_stream<ST>(P.g_out, vb + cc, gn);
+                st_stream<ST>(P.b_out, vb + cc, bn);
             }
         }
     }
