@@ -267,6 +267,10 @@ void velocity_tables(const Resolved& r, std::vector<double>& vel, std::vector<do
         }
         v[VE_W] = w;
         v[VE_HX2] = 0.5 * x2;
+        for (int d = 0; d < D; ++d) {
+            v[VE_WXI0 + d] = w * nodes[d][m[d]];
+            for (int e = 0; e < D; ++e) v[VE_WXX + 3 * d + e] = w * nodes[d][m[d]] * nodes[e][m[e]];
+        }
     }
     axis.clear();
     for (int d = 0; d < 3; ++d) axis.insert(axis.end(), nodes[d].begin(), nodes[d].end());
@@ -301,6 +305,7 @@ void fill_problem(const Resolved& r, char* base, Problem& P) {
     P.mu_ref = r.mu_ref;
     P.T_ref = r.T_ref;
     P.tau_inv = r.tau_inv;
+    P.hxi0 = (r.vmax[0] - r.vmin[0]) / (r.nv[0] - 1);
     P.vel = (const double*)(base + r.off_vel);
     P.axis_xi = (const double*)(base + r.off_axis);
     P.axis_w = P.axis_xi + (r.nv[0] + r.nv[1] + r.nv[2]);

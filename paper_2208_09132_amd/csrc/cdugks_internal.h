@@ -25,9 +25,10 @@ enum { PC_A = 0, PC_INV2RT, PC_CRT2, PC_BETA, PC_BETAB, PC_ETA, PC_HU2, PC_U0, N
 enum { PF_A = 0, PF_INV2RT, PF_CRT2, PF_IG, PF_BG, PF_IB, PF_BB, PF_EB, PF_HU2, PF_U0,
        NFP = PF_U0 + 3 };
 
-// Per-velocity constants ([V][NVEL]): xi, weight, |xi|^2/2 and the Courant-like
-// numbers lambda_d = (dt/2) xi_d / dx_d.
-enum { VE_XI0 = 0, VE_W = 3, VE_HX2 = 4, VE_LAM0 = 5, NVEL = 8 };
+// Per-velocity constants ([V][NVEL]): xi, weight, |xi|^2/2, the Courant-like
+// numbers lambda_d = (dt/2) xi_d / dx_d, and the weighted products used by the
+// face sums, w xi_e and w xi_d xi_e ([d][e], 3 x 3).
+enum { VE_XI0 = 0, VE_W = 3, VE_HX2 = 4, VE_LAM0 = 5, VE_WXI0 = 8, VE_WXX = 11, NVEL = 20 };
 
 constexpr int MAX_NSUM = 9;  // 2D+3 face sums for D = 3
 
@@ -47,6 +48,7 @@ struct Problem {
     long long N, NE;
     double dx[3], inv_dx[3];
     double dt, gamma, Pr, R, c_int, omega, mu_ref, T_ref, tau_inv;
+    double hxi0;          // node spacing of velocity axis 0 (the fastest velocity index)
     const double* vel;    // [V][NVEL]
     const double* axis_xi;  // concatenated 1-D nodes, offsets 0, nv0, nv0+nv1
     const double* axis_w;   // concatenated 1-D weights

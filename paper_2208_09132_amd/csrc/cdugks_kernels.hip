@@ -44,15 +44,12 @@ __device__ __forceinline__ int map_coord(int x, int n, int bc) {
     return x < 0 ? 0 : (x >= n ? n - 1 : x);
 }
 
-// Reciprocal to full double precision without the IEEE division sequence:
-// hardware estimate refined by two Newton-Raphson steps (each squares the
-// relative error).  Used where the operand is a nonzero finite sum.
-__device__ __forceinline__ double fast_rcp(double s) {
-    double r = __builtin_amdgcn_rcp(s);
-    double e = fma(-s, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-s, r, 1.0);
-    return fma(r, e, r);
+// Reciprocal from the hardware estimate (relative error below 1e-7) refined
+// by one Newton-Raphson step, which squares the error to about 2e-15.  Used
+// where the operand is a nonzero finite sum.
+__device__ __forceinline__ double rcp_nr(double s) {
+    const double r = __builtin_amdgcn_rcp(s);
+    return fma(r, fma(-s, r, 1.0), r);
 }
 
 // Van Leer limiter (eq. VanLeer) in the harmonic-mean form: identical to
@@ -61,7 +58,7 @@ __device__ __forceinline__ double fast_rcp(double s) {
 // its value is discarded by the select.
 __device__ __forceinline__ double van_leer(double a, double b) {
     double p = a * b;
-    double v = (p + p) * fast_rcp(a + b);
+    double v = (p + p) * rcp_nr(a + b);
     return p > 0.0 ? v : 0.0;
 }
 
@@ -260,8 +257,12 @@ struct Vel {
 // neither occupy vector-memory slots nor delay waits on the field loads.
 typedef const __attribute__((address_space(4))) double* const_dptr;
 
+__device__ __forceinline__ const_dptr vel_ptr(const double* vel, int i) {
+    return (const_dptr)(const void*)(vel + (long long)i * NVEL);
+}
+
 __device__ __forceinline__ Vel load_vel(const double* vel, int i) {
-    const_dptr v = (const_dptr)(const void*)(vel + (long long)i * NVEL);
+    const_dptr v = vel_ptr(vel, i);
     Vel r;
     r.xi[0] = v[0]; r.xi[1] = v[1]; r.xi[2] = v[2];
     r.w = v[VE_W]; r.hx2 = v[VE_HX2];
@@ -269,25 +270,31 @@ __device__ __forceinline__ Vel load_vel(const double* vel, int i) {
     return r;
 }
 
-// Equilibria, Z and the quarter-step fields at one (cell, velocity):
+// Z and the quarter-step fields at one (cell, velocity), given g_eq:
 // phi_bar_plus = phi + (h/2)(phi_eq - phi)/tau + (h/2) S, S_b = Z (g - g_eq)/tau_bg.
-// Returns g_eq.
 template <int D>
-__device__ __forceinline__ double quarter_step(const CellCoef& k, const Vel& v, double g, double b,
-                                               double& qg, double& qb) {
-    double c2 = 0.0, xu = 0.0;
+__device__ __forceinline__ void quarter_step_eq(const CellCoef& k, const Vel& v, double geq, double g, double b,
+                                                double& qg, double& qb) {
+    double xu = 0.0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        double x = v.xi[d] - k.u[d];
-        c2 += x * x;
-        xu += v.xi[d] * k.u[d];
-    }
-    double geq = k.A * exp(-c2 * k.inv2RT);
+    for (int d = 0; d < D; ++d) xu += v.xi[d] * k.u[d];
     double beq = (v.hx2 + k.cRT2) * geq;
     double Z = xu - k.hu2;
     qg = g + k.beta * (geq - g);
     qb = b + k.betab * (beq - b) + k.eta * Z * (g - geq);
-    return geq;
+}
+
+// The same with the equilibrium evaluated directly.
+template <int D>
+__device__ __forceinline__ void quarter_step(const CellCoef& k, const Vel& v, double g, double b, double& qg,
+                                             double& qb) {
+    double c2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        double x = v.xi[d] - k.u[d];
+        c2 += x * x;
+    }
+    quarter_step_eq<D>(k, v, k.A * exp(-c2 * k.inv2RT), g, b, qg, qb);
 }
 
 // Value of phi_bar at a face centre at t_{n+1/2}: upwind cell u (LDS indices
@@ -367,19 +374,68 @@ struct FaceCoef {
     }
     // phi at the face from phi_bar: g = ig gbar + bg g_eq; b likewise with the
     // S_b source at the face evaluated with the face g.
-    __device__ __forceinline__ void invert(const Vel& v, double vg, double vb, double& gF, double& bF) const {
-        double c2 = 0.0, xu = 0.0;
+
+    __device__ __forceinline__ void invert(const Vel& v, double geq, double vg, double vb, double& gF,
+                                           double& bF) const {
+        double xu = 0.0;
 #pragma unroll
-        for (int e = 0; e < D; ++e) {
-            double x = v.xi[e] - u[e];
-            c2 += x * x;
-            xu += v.xi[e] * u[e];
-        }
-        double geq = A * exp(-c2 * inv2RT);
+        for (int e = 0; e < D; ++e) xu += v.xi[e] * u[e];
         double beq = (v.hx2 + cRT2) * geq;
         double Z = xu - hu2;
         gF = ig * vg + bg * geq;
         bF = ib * vb + bb * beq + eb * Z * (gF - geq);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Maxwellian by recurrence along the fastest velocity axis.  The nodes of
+// velocity axis 0 are uniform (spacing h); with x_k = xi_k - u_x, s = 1/(2RT)
+// and everything else fixed,
+//   g_eq(k+1) = g_eq(k) R_k,  R_k = exp(-(2 x_k + h) h s),  R_{k+1} = R_k C,
+//   C = exp(-2 h^2 s).
+// g_eq and R are set from direct exponentials at every WALK-th node of axis 0
+// (anchors; a row of the velocity grid starts with one), which bounds the
+// rounding drift of the products to about WALK^2 ulp.  A block whose
+// exponents could leave the range where the products stay normal numbers
+// uses direct exponentials throughout.  The value at a node depends only on
+// the node, not on where a velocity slice starts: a slice starting inside a
+// block walks from that block's anchor.
+// ---------------------------------------------------------------------------
+constexpr int WALK = 8;
+
+template <int D>
+__device__ __forceinline__ double maxwellian(double A, double s, const double* u, const Vel& v) {
+    double c2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        const double x = v.xi[e] - u[e];
+        c2 += x * x;
+    }
+    return A * exp(-c2 * s);
+}
+
+struct GaussWalk {
+    double E, R, C;
+    bool ok;
+    __device__ __forceinline__ void init(double s, double h) { C = exp(-2.0 * h * h * s); }
+    // anchor at the current node (its axis-0 coordinate is v.xi[0])
+    template <int D>
+    __device__ __forceinline__ void anchor(double A, double s, const double* u, const Vel& v, double h) {
+        const double x = v.xi[0] - u[0];
+        E = maxwellian<D>(A, s, u, v);
+        R = exp(-(x + x + h) * h * s);
+        const double m = fmax(fabs(x), fabs(x + (WALK - 1) * h));
+        ok = m * m * s < 600.0 && (m + m + h) * h * s < 600.0 && h * h * s < 300.0;
+    }
+    __device__ __forceinline__ void advance() {
+        E *= R;
+        R *= C;
+    }
+    template <int D>
+    __device__ __forceinline__ double value(double A, double s, const double* u, const Vel& v) const {
+        double geq = E;
+        if (!ok) geq = maxwellian<D>(A, s, u, v);
+        return geq;
     }
 };
 
@@ -549,8 +605,32 @@ struct FaceSumKernel {
             }
         }
         const long long fstride = (long long)P.V * NE;  // per (d, field) block of FV
+
+        // Maxwellians of the q-box slots by recurrence along velocity axis 0
+        // (when the slot coefficients live in registers)
+        constexpr bool WALKER = G::CACHE_COEF;
+        const double h = P.hxi0;
+        const int nvx = P.nv[0];
+        GaussWalk wq[WALKER ? NSLOT : 1];
+        if constexpr (WALKER) {
+#pragma unroll
+            for (int k = 0; k < NSLOT; ++k) wq[k].init(kq[k].inv2RT, h);
+        }
+        int ix = v0 % nvx;
+
         for (int i = v0; i < v1; ++i) {
             const Vel v = load_vel(P.vel, i);
+            if constexpr (WALKER) {
+                if (i == v0 || ix % WALK == 0) {
+                    const int a0 = ix - ix % WALK;
+                    const Vel va = a0 == ix ? v : load_vel(P.vel, i - (ix - a0));
+#pragma unroll
+                    for (int k = 0; k < NSLOT; ++k) wq[k].template anchor<D>(kq[k].A, kq[k].inv2RT, kq[k].u, va, h);
+                    for (int j = a0; j < ix; ++j)
+#pragma unroll
+                        for (int k = 0; k < NSLOT; ++k) wq[k].advance();
+                }
+            }
             const long long vb = (long long)i * N;
             const int buf = NBUF == 2 ? ((i - v0) & 1) : 0;
             CT* const sq0 = sm.q[buf][0];
@@ -588,7 +668,8 @@ struct FaceSumKernel {
                     }
                     double qg, qb;
                     if constexpr (G::CACHE_COEF) {
-                        quarter_step<D>(kq[k], v, g, b, qg, qb);
+                        const double geq = wq[k].template value<D>(kq[k].A, kq[k].inv2RT, kq[k].u, v);
+                        quarter_step_eq<D>(kq[k], v, geq, g, b, qg, qb);
                     } else if constexpr (COEF_LDS) {
                         const double* o = sm.kc + r;
                         CellCoef kk;
@@ -631,7 +712,6 @@ struct FaceSumKernel {
             // stage 3: left face of the own cell along each d
 #pragma unroll
             for (int d = 0; d < D; ++d) {
-                const double xd = v.xi[d];
                 int dxo = d == 0, dyo = d == 1, dzo = d == 2;
                 CT vgc, vbc;
                 face_pair<D, G, CT>(sqp, sap, d, G::qidx(tx - dxo, ty - dyo, tz - dzo),
@@ -643,14 +723,20 @@ struct FaceSumKernel {
                     st_stream<ST>(P.FV, o, vg);
                     st_stream<ST>(P.FV, o + fstride, vb2);
                 }
-                const double wg = v.w * vg, wb = v.w * vb2;
-                acc[d][0] += wg;
+                // weighted velocity products come from the table (uniform)
+                const const_dptr vp = vel_ptr(P.vel, i);
+                acc[d][0] += v.w * vg;
 #pragma unroll
-                for (int e = 0; e < D; ++e) acc[d][1 + e] += v.xi[e] * wg;
-                acc[d][D + 1] += wb;
+                for (int e = 0; e < D; ++e) acc[d][1 + e] += vp[VE_WXI0 + e] * vg;
+                acc[d][D + 1] += v.w * vb2;
 #pragma unroll
-                for (int e = 0; e < D; ++e) acc[d][D + 2 + e] += xd * v.xi[e] * wg;
-                acc[d][2 * D + 2] += xd * wb;
+                for (int e = 0; e < D; ++e) acc[d][D + 2 + e] += vp[VE_WXX + 3 * d + e] * vg;
+                acc[d][2 * D + 2] += vp[VE_WXI0 + d] * vb2;
+            }
+            if constexpr (WALKER) {
+#pragma unroll
+                for (int k = 0; k < NSLOT; ++k) wq[k].advance();
+                if (++ix == nvx) ix = 0;
             }
             // single-buffered: the next velocity must not overwrite q and a
             // before every thread has read them; double-buffered: the next
@@ -717,12 +803,54 @@ struct UpdateKernel {
         // constant parts of eq. phiupdate
         const double inv_g = 1.0 / (1.0 + 2.0 * k1.beta), inv_b = 1.0 / (1.0 + 2.0 * k1.betab);
 
-        // FP64: two velocities per trip (twice the loads in flight per wave);
-        // FP32 keeps one, which leaves room for a third wave per SIMD
-        constexpr int UNROLL = sizeof(ST) == 8 ? 2 : 1;
+        // Maxwellians by recurrence along velocity axis 0 for FP64 storage in
+        // 1-D and 2-D.  The 3-D kernel has no registers to spare, and the FP32
+        // kernel runs a third wave per SIMD without the recurrence state,
+        // which outweighs the exponentials it saves.
+        constexpr bool WALKER = D <= 2 && sizeof(ST) == 8;
+        const double h = P.hxi0;
+        const int nvx = P.nv[0];
+        GaussWalk w0, w1, wl[D], wr[D];
+        if constexpr (WALKER) {
+            w0.init(k0.inv2RT, h);
+            w1.init(k1.inv2RT, h);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                wl[d].init(fcl[d].inv2RT, h);
+                wr[d].init(fcr[d].inv2RT, h);
+            }
+        }
+        int ix = v0 % nvx;
+
+        // FP64 without the recurrence: two velocities per trip (twice the
+        // loads in flight per wave)
+        constexpr int UNROLL = sizeof(ST) == 8 && !WALKER ? 2 : 1;
 #pragma unroll UNROLL
         for (int i = v0; i < v1; ++i) {
             const Vel v = load_vel(P.vel, i);
+            if constexpr (WALKER) {
+                if (i == v0 || ix % WALK == 0) {
+                    const int a0 = ix - ix % WALK;
+                    // a slice starting inside a block walks from its anchor
+                    const Vel va = a0 == ix ? v : load_vel(P.vel, i - (ix - a0));
+                    w0.anchor<D>(k0.A, k0.inv2RT, k0.u, va, h);
+                    w1.anchor<D>(k1.A, k1.inv2RT, k1.u, va, h);
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        wl[d].template anchor<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, va, h);
+                        wr[d].template anchor<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, va, h);
+                    }
+                    for (int j = a0; j < ix; ++j) {
+                        w0.advance();
+                        w1.advance();
+#pragma unroll
+                        for (int d = 0; d < D; ++d) {
+                            wl[d].advance();
+                            wr[d].advance();
+                        }
+                    }
+                }
+            }
             const long long vb = (long long)i * N;
             const double g = ld<ST>(P.g_in, vb + cc);
             const double b = ld<ST>(P.b_in, vb + cc);
@@ -730,24 +858,23 @@ struct UpdateKernel {
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 const long long o = (long long)(2 * d) * fstride + (long long)i * NE;
+                const double eql = WALKER ? wl[d].template value<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v)
+                                          : maxwellian<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v);
+                const double eqr = WALKER ? wr[d].template value<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v)
+                                          : maxwellian<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v);
                 double gl, bl, gr, br;
-                fcl[d].invert(v, ld<ST>(P.FV, o + fl[d]), ld<ST>(P.FV, o + fstride + fl[d]), gl, bl);
-                fcr[d].invert(v, ld<ST>(P.FV, o + fr[d]), ld<ST>(P.FV, o + fstride + fr[d]), gr, br);
+                fcl[d].invert(v, eql, ld<ST>(P.FV, o + fl[d]), ld<ST>(P.FV, o + fstride + fl[d]), gl, bl);
+                fcr[d].invert(v, eqr, ld<ST>(P.FV, o + fr[d]), ld<ST>(P.FV, o + fstride + fr[d]), gr, br);
                 const double sxd = v.xi[d] * P.inv_dx[d];
                 Fg += sxd * (gr - gl);
                 Fb += sxd * (br - bl);
             }
-            double c20 = 0.0, c21 = 0.0, xu0 = 0.0;
+            double xu0 = 0.0;
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
-                double x0 = v.xi[d] - k0.u[d], x1 = v.xi[d] - k1.u[d];
-                c20 += x0 * x0;
-                c21 += x1 * x1;
-                xu0 += v.xi[d] * k0.u[d];
-            }
-            const double geq0 = k0.A * exp(-c20 * k0.inv2RT);
+            for (int d = 0; d < D; ++d) xu0 += v.xi[d] * k0.u[d];
+            const double geq0 = WALKER ? w0.value<D>(k0.A, k0.inv2RT, k0.u, v) : maxwellian<D>(k0.A, k0.inv2RT, k0.u, v);
             const double beq0 = (v.hx2 + k0.cRT2) * geq0;
-            const double geq1 = k1.A * exp(-c21 * k1.inv2RT);
+            const double geq1 = WALKER ? w1.value<D>(k1.A, k1.inv2RT, k1.u, v) : maxwellian<D>(k1.A, k1.inv2RT, k1.u, v);
             const double beq1 = (v.hx2 + k1.cRT2) * geq1;
             const double Z0 = xu0 - k0.hu2;
             // eq. phiupdate with dt/(2 tau) = 2 beta and dt S_b = 4 eta Z (g - g_eq)
@@ -758,6 +885,16 @@ struct UpdateKernel {
             if (inside) {
                 st_stream<ST>(P.g_out, vb + cc, gn);
                 st_stream<ST>(P.b_out, vb + cc, bn);
+            }
+            if constexpr (WALKER) {
+                w0.advance();
+                w1.advance();
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    wl[d].advance();
+                    wr[d].advance();
+                }
+                if (++ix == nvx) ix = 0;
             }
         }
     }
