@@ -69,6 +69,11 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
         r.NE *= r.ne[d];
         r.V *= r.nv[d];
     }
+    // index ranges the kernels assume: 32-bit cell and face indices, 32-bit
+    // velocity indices, and at most 2^40 phase-space points per problem
+    if (r.NE >= (1LL << 31) || r.V >= (1LL << 24) || r.N * r.V > (1LL << 40))
+        return fail(CDUGKS_ERR_INVALID, "problem too large (%lld cells x %lld velocities)", (long long)r.N,
+                    (long long)r.V);
     if (ve->quadrature != CDUGKS_QUAD_TRAPEZOID && ve->quadrature != CDUGKS_QUAD_BOOLE)
         return fail(CDUGKS_ERR_INVALID, "unknown quadrature %d", ve->quadrature);
     if (!(pa->gamma > 1.0) || pa->gamma > 5.0 / 3.0 + 1e-12)
@@ -186,6 +191,7 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
         r.off_W[k] = take((size_t)(D + 2) * r.N * 8);
         r.off_P[k] = take((size_t)NPC * r.N * 8);
     }
+    r.off_q = quarter_stored(D) ? take(2 * NV * es) : 0;
     r.off_FV = take((size_t)D * 2 * r.V * r.NE * es);
     r.off_FS = take((size_t)r.nslices * D * (2 * D + 3) * r.NE * 8);
     r.off_FP = take((size_t)D * NFP * r.NE * 8);
@@ -309,6 +315,10 @@ void fill_problem(const Resolved& r, char* base, Problem& P) {
     P.vel = (const double*)(base + r.off_vel);
     P.axis_xi = (const double*)(base + r.off_axis);
     P.axis_w = P.axis_xi + (r.nv[0] + r.nv[1] + r.nv[2]);
+    if (quarter_stored(r.D)) {
+        P.qg = base + r.off_q;
+        P.qb = base + r.off_q + (size_t)r.N * r.V * (r.storage == CDUGKS_STORE_F64 ? 8 : 4);
+    }
     P.FV = base + r.off_FV;
     P.FS = (double*)(base + r.off_FS);
     P.FP = (double*)(base + r.off_FP);

@@ -32,6 +32,14 @@ enum { VE_XI0 = 0, VE_W = 3, VE_HX2 = 4, VE_LAM0 = 5, VE_WXI0 = 8, VE_WXX = 11, 
 
 constexpr int MAX_NSUM = 9;  // 2D+3 face sums for D = 3
 
+// Whether the update kernel also stores the next step's quarter-step fields
+// phi_bar_plus (eq. phibarplus, from the new state and the new equilibrium it
+// has at hand), so that the face-sum kernel loads them instead of evaluating
+// the equilibrium on its whole halo box.  Done in 3-D, where that box is 5.9
+// times the tile; in 1-D and 2-D (1.7 times) the extra 2 stores per update
+// cost the update kernel about what the face-sum kernel saves.
+constexpr bool quarter_stored(int D) { return D == 3; }
+
 // Device-side description of one problem.  Pointers are device addresses.
 struct Problem {
     int D;
@@ -56,6 +64,8 @@ struct Problem {
     const void* g_in; const void* b_in; void* g_out; void* b_out;
     const double* W_in; double* W_out;
     const double* P_in; double* P_out;
+    void* qg;     // quarter-step fields [V][N] for g and b, storage precision
+    void* qb;     // (null unless quarter_stored(D))
     void* FV;     // face values phi_bar [D][2][V][NE], storage precision
     double* FS;   // face partial sums [nslices][D][2D+3][NE]
     double* FP;   // face coefficients [D][NFP][NE]

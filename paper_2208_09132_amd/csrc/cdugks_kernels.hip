@@ -297,6 +297,29 @@ __device__ __forceinline__ void quarter_step(const CellCoef& k, const Vel& v, do
     quarter_step_eq<D>(k, v, k.A * exp(-c2 * k.inv2RT), g, b, qg, qb);
 }
 
+// Quarter-step fields of the initial state (when they are stored): the same
+// arithmetic the update kernel applies to each new state.
+template <int D, typename ST>
+__global__ __launch_bounds__(256) void k_init_quarter(Problem P) {
+    long long idx = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long N = P.N;
+    if (idx >= N * P.V) return;
+    const long long i = idx / N, c = idx - i * N;
+    const CellCoef k = load_coef(P.P_in, N, c);
+    const Vel v = load_vel(P.vel, (int)i);
+    double c2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const double x = v.xi[d] - k.u[d];
+        c2 += x * x;
+    }
+    const double geq = k.A * exp(-c2 * k.inv2RT);
+    double qg, qb;
+    quarter_step_eq<D>(k, v, geq, ld<ST>(P.g_in, idx), ld<ST>(P.b_in, idx), qg, qb);
+    st<ST>(P.qg, idx, qg);
+    st<ST>(P.qb, idx, qb);
+}
+
 // Value of phi_bar at a face centre at t_{n+1/2}: upwind cell u (LDS indices
 // qi, ai), side s = +1 when the face is u's right face, -1 when its left face.
 //   v = q(u) + s a_d/2 - sum_e lambda_e (a_e + s b_de/2),
@@ -499,7 +522,11 @@ struct FaceSumKernel {
     // when the q-box points do not fit in registers, the cell coefficients
     // of the whole box are staged in LDS once (3-D FP32; the FP64 3-D box does
     // not fit and reads them from memory)
-    static constexpr bool COEF_LDS = !G::CACHE_COEF && sizeof(CT) == 4;
+    // With stored quarter-step fields the q box is loaded, not computed.
+    static constexpr bool QS = quarter_stored(D);
+    // cell coefficients of the q-box slots in registers
+    static constexpr bool KQ = G::CACHE_COEF && !QS;
+    static constexpr bool COEF_LDS = !G::CACHE_COEF && sizeof(CT) == 4 && !QS;
 
     // 1-D and 2-D alternate two LDS buffers between consecutive velocities,
     // which removes the barrier that would otherwise end each velocity
@@ -528,7 +555,7 @@ struct FaceSumKernel {
         // periodic wrap / outflow clamp
         long long srcq[NSLOT];
         int lq[NSLOT];
-        CellCoef kq[G::CACHE_COEF ? NSLOT : 1];
+        CellCoef kq[KQ ? NSLOT : 1];
         {
             int lx = tid % G::TX, ly = (tid / G::TX) % G::TY, lz = tid / (G::TX * G::TY);
             lq[0] = G::qidx(lx, ly, lz);
@@ -547,7 +574,7 @@ struct FaceSumKernel {
                 int cy = D >= 2 ? map_coord(oy + ry - G::OQY, P.n[1], P.bc[1]) : 0;
                 int cz = D >= 3 ? map_coord(oz + rz - G::OQZ, P.n[2], P.bc[2]) : 0;
                 srcq[k] = cx + (long long)P.n[0] * (cy + (long long)P.n[1] * cz);
-                if constexpr (G::CACHE_COEF) kq[k] = load_coef(P.P_in, N, srcq[k]);
+                if constexpr (KQ) kq[k] = load_coef(P.P_in, N, srcq[k]);
             }
         }
         if constexpr (COEF_LDS) {
@@ -594,21 +621,23 @@ struct FaceSumKernel {
 
         // software pipelining: the next velocity's g, b are loaded while the
         // current one is processed (when the q-box slots fit in registers)
-        constexpr bool PREFETCH = NSLOT <= 2;
+        constexpr bool PREFETCH = NSLOT <= 2 || QS;
+        const void* const src_g = QS ? P.qg : P.g_in;
+        const void* const src_b = QS ? P.qb : P.b_in;
         double pg[NSLOT], pbv[NSLOT];
         if constexpr (PREFETCH) {
 #pragma unroll
             for (int k = 0; k < NSLOT; ++k) {
                 const long long a0 = (long long)(v0 < v1 ? v0 : 0) * N + srcq[k];
-                pg[k] = ld<ST>(P.g_in, a0);
-                pbv[k] = ld<ST>(P.b_in, a0);
+                pg[k] = ld<ST>(src_g, a0);
+                pbv[k] = ld<ST>(src_b, a0);
             }
         }
         const long long fstride = (long long)P.V * NE;  // per (d, field) block of FV
 
         // Maxwellians of the q-box slots by recurrence along velocity axis 0
         // (when the slot coefficients live in registers)
-        constexpr bool WALKER = G::CACHE_COEF;
+        constexpr bool WALKER = KQ;
         const double h = P.hxi0;
         const int nvx = P.nv[0];
         GaussWalk wq[WALKER ? NSLOT : 1];
@@ -648,8 +677,8 @@ struct FaceSumKernel {
                 for (int k = 0; k < NSLOT; ++k) {
                     cg[k] = pg[k];
                     cbv[k] = pbv[k];
-                    pg[k] = ld<ST>(P.g_in, nb + srcq[k]);
-                    pbv[k] = ld<ST>(P.b_in, nb + srcq[k]);
+                    pg[k] = ld<ST>(src_g, nb + srcq[k]);
+                    pbv[k] = ld<ST>(src_b, nb + srcq[k]);
                 }
             }
 
@@ -663,11 +692,14 @@ struct FaceSumKernel {
                         g = cg[k];
                         b = cbv[k];
                     } else {
-                        g = ld<ST>(P.g_in, vb + srcq[k]);
-                        b = ld<ST>(P.b_in, vb + srcq[k]);
+                        g = ld<ST>(src_g, vb + srcq[k]);
+                        b = ld<ST>(src_b, vb + srcq[k]);
                     }
                     double qg, qb;
-                    if constexpr (G::CACHE_COEF) {
+                    if constexpr (QS) {
+                        qg = g;
+                        qb = b;
+                    } else if constexpr (KQ) {
                         const double geq = wq[k].template value<D>(kq[k].A, kq[k].inv2RT, kq[k].u, v);
                         quarter_step_eq<D>(kq[k], v, geq, g, b, qg, qb);
                     } else if constexpr (COEF_LDS) {
@@ -777,15 +809,16 @@ struct UpdateKernel {
                 r /= P.n[e];
             }
         }
-        // left and right faces along each d (periodic wrap at the right end)
-        long long fl[D], fr[D];
+        // left and right faces along each d (periodic wrap at the right end);
+        // face indices fit 32 bits (checked at set-up)
+        unsigned fl[D], fr[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             int rc[3] = {co[0], co[1], co[2]};
-            fl[d] = rc[0] + (long long)P.ne[0] * (rc[1] + (long long)P.ne[1] * rc[2]);
+            fl[d] = (unsigned)(rc[0] + (long long)P.ne[0] * (rc[1] + (long long)P.ne[1] * rc[2]));
             rc[d] += 1;
             if (P.bc[d] == 0 && rc[d] == P.n[d]) rc[d] = 0;
-            fr[d] = rc[0] + (long long)P.ne[0] * (rc[1] + (long long)P.ne[1] * rc[2]);
+            fr[d] = (unsigned)(rc[0] + (long long)P.ne[0] * (rc[1] + (long long)P.ne[1] * rc[2]));
         }
         const CellCoef k0 = load_coef(P.P_in, N, cc);
         const CellCoef k1 = load_coef(P.P_out, N, cc);
@@ -885,6 +918,13 @@ struct UpdateKernel {
             if (inside) {
                 st_stream<ST>(P.g_out, vb + cc, gn);
                 st_stream<ST>(P.b_out, vb + cc, bn);
+                if constexpr (quarter_stored(D)) {
+                    // next step's phi_bar_plus from the state as stored
+                    double qg, qb;
+                    quarter_step_eq<D>(k1, v, geq1, (double)(ST)gn, (double)(ST)bn, qg, qb);
+                    st_stream<ST>(P.qg, vb + cc, qg);
+                    st_stream<ST>(P.qb, vb + cc, qb);
+                }
             }
             if constexpr (WALKER) {
                 w0.advance();
@@ -934,7 +974,7 @@ __global__ __launch_bounds__(WG) void k_face_sums_batched(const Problem* probs, 
 
 // update grid: blocks of 256 consecutive cells x velocity slices
 template <int D, typename ST>
-__global__ __launch_bounds__(WG) void k_update(Problem P) {
+__global__ __launch_bounds__(WG, 2) void k_update(Problem P) {
     const int nblk = (int)((P.N + WG - 1) / WG);
     int q = xcd_remap(blockIdx.x, gridDim.x);
     int blk = q % nblk, slice = q / nblk;
@@ -1163,15 +1203,7 @@ __global__ __launch_bounds__(WG) void k_to_f64(long long n, const void* src, dou
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(long long n) { return (unsigned)((n + WG - 1) / WG); }
 
-hipError_t launch_init(const Problem& P, const double* rho, const double* u, const double* T,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(k_init_cells, dim3(blocks_for(P.N)), dim3(WG), 0, s, P, rho, u, T);
-    if (P.storage == 0)
-        hipLaunchKernelGGL(k_init_phi<double>, dim3(blocks_for(P.N * P.V)), dim3(WG), 0, s, P);
-    else
-        hipLaunchKernelGGL(k_init_phi<float>, dim3(blocks_for(P.N * P.V)), dim3(WG), 0, s, P);
-    return hipGetLastError();
-}
+
 
 #define CDG_DISPATCH(STORAGE, DIM, MACRO)                            \
     do {                                                             \
@@ -1185,6 +1217,22 @@ hipError_t launch_init(const Problem& P, const double* rho, const double* u, con
             else MACRO(3, float);                                    \
         }                                                            \
     } while (0)
+
+hipError_t launch_init(const Problem& P, const double* rho, const double* u, const double* T,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_init_cells, dim3(blocks_for(P.N)), dim3(WG), 0, s, P, rho, u, T);
+    if (P.storage == 0)
+        hipLaunchKernelGGL(k_init_phi<double>, dim3(blocks_for(P.N * P.V)), dim3(WG), 0, s, P);
+    else
+        hipLaunchKernelGGL(k_init_phi<float>, dim3(blocks_for(P.N * P.V)), dim3(WG), 0, s, P);
+    if (quarter_stored(P.D)) {
+        const dim3 grid(blocks_for(P.N * P.V));
+#define CDG_L(D, ST) hipLaunchKernelGGL((k_init_quarter<D, ST>), grid, dim3(256), 0, s, P)
+        CDG_DISPATCH(P.storage, P.D, CDG_L);
+#undef CDG_L
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_face_sums(const Problem& P, hipStream_t s) {
     unsigned nb = (unsigned)(P.tiles1[0] * P.tiles1[1] * P.tiles1[2] * P.nslices);
