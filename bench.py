@@ -30,6 +30,21 @@ KERNEL_BYTES = {"face_sums": {"f64": 16.0, "f32": 8.0}, "update": {"f64": 32.0, 
 PHASES = ["face_sums", "face_close", "cell_close", "update"]
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_face_sums_kh2d_256_v28_fp64.md")
+
+
+def profiled_traffic(config: str, kernel: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    PMC summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), or
+    None when that summary was taken from other kernel sources or covers
+    another kernel or workload."""
+    from paper_2208_09132_amd import profiling as pf
+    rec = pf.load_record(TRAFFIC_PROFILE)
+    if config != "kh" or kernel != "face_sums" or rec is None or rec.get("digest") != pf.source_digest():
+        return None
+    return rec
+
+
 def workload(name: str, storage: str):
     from paper_2208_09132_amd import workloads as wl
     if name == "kh":
@@ -41,7 +56,7 @@ def workload(name: str, storage: str):
     raise SystemExit(f"unknown config {name}")
 
 
-def time_gpu(prob, steps: int, warmup: int):
+def time_gpu(prob, steps: int, warmup: int, copy_calibration: bool = False):
     import torch
     from paper_2208_09132_amd import cdugks as cd
 
@@ -57,6 +72,10 @@ def time_gpu(prob, steps: int, warmup: int):
     wall = time.perf_counter() - t0
     # per-kernel durations from HIP events on the context's stream
     phase_ms = s.profile_phases(max(3, min(steps, 10)))
+    if copy_calibration:
+        # two dispatches of the library's storage-to-FP64 copy (N V values
+        # each): a plain copy of known size for calibrating HBM counters
+        s.distributions()
     s.close()
     return N, V, wall, phase_ms
 
@@ -168,13 +187,16 @@ def cpu_baseline(prob, budget_s: float = 20.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    # the GPU clock settles over the first ~20 steps (kernel traces show it)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="kh")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--batched-problems", type=int, default=256)
     ap.add_argument("--served-requests", type=int, default=16)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run the library's FP64 distribution copy (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design note, "
@@ -185,7 +207,7 @@ def main():
     torch.cuda.set_device(0)
 
     name, prob = workload(args.config, "f64")
-    N, V, wall, phase_ms = time_gpu(prob, args.steps, args.warmup)
+    N, V, wall, phase_ms = time_gpu(prob, args.steps, args.warmup, args.copy_calibration)
     ups = N * V * args.steps / wall
     ms_step = 1e3 * wall / args.steps
 
@@ -194,8 +216,11 @@ def main():
     dom_name = PHASES[dom]
     kb = KERNEL_BYTES.get(dom_name, {"f64": 0.0})["f64"]
     achieved = kb * N * V / (phase_ms[dom] * 1e-3) / 1e9
+    rec = profiled_traffic(args.config, dom_name)
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": rec["traffic_bytes"] if rec else None,
+                "traffic_unit": "bytes per launch",
+                "traffic_per_update": rec["traffic_bytes"] / (N * V) if rec else None,
                 "kernel_ms": float(phase_ms[dom]), "phase_ms": {k: float(v) for k, v in zip(PHASES, phase_ms)},
                 "algorithmic_bytes_per_update": kb,
                 "step_algorithmic_frac": ALGO_BYTES["f64"] * ups / 1e9 / HBM_PEAK_GBS}

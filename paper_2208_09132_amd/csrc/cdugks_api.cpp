@@ -160,18 +160,31 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
     // on the problem and the device type, never on what else is running.
     long long R1, R2;
     resident_slots(D, r.storage, &R1, &R2);
-    auto plan = [&](long long ntiles, long long R) {
-        if (ntiles >= R) return 1LL;
-        long long s = (R + ntiles / 2) / ntiles;
-        return std::max(1LL, s);
-    };
     // at least 16 velocities per slice so the per-tile set-up stays amortised
     const long long smax = std::max(1LL, r.V / 16);
+    // Workgroups of one launch run in rounds of R; a last round that is
+    // mostly empty costs as much as a full one.  Take the smallest split whose
+    // work items fill their rounds to 90%, else the best filling one.
+    auto plan = [&](long long ntiles, long long R) {
+        if (R <= 0) return 1LL;
+        long long best = 1;
+        double best_fill = -1.0;
+        for (long long s = 1; s <= smax && s <= 64; ++s) {
+            const long long items = ntiles * s;
+            const long long rounds = (items + R - 1) / R;
+            const double fill = (double)items / (double)(rounds * R);
+            if (fill >= 0.9) return s;
+            if (fill > best_fill + 1e-12) {
+                best_fill = fill;
+                best = s;
+            }
+        }
+        return best;
+    };
     int slices = pa->velocity_slices;
-    long long s1 = slices > 0 ? std::min<long long>(slices, r.V) : std::min(plan(nt1, R1), smax);
+    long long s1 = slices > 0 ? std::min<long long>(slices, r.V) : plan(nt1, R1);
     r.nslices = (int)std::max(1LL, s1);
-    long long s2 = std::min(plan(nt2, R2), smax);
-    r.nslices_upd = (int)std::max(1LL, s2);
+    r.nslices_upd = (int)std::max(1LL, plan(nt2, R2));
     // the autotuner may have picked another update split for this class
     // (speed only: the update's result does not depend on it)
     if (int tu = tuned_update_slices(r); tu > 0) r.nslices_upd = (int)std::min<long long>(tu, r.V);
