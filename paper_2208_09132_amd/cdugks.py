@@ -17,7 +17,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcdugks.so")
+# the in-tree build; CDUGKS_LIBRARY may name another build of the same ABI
+LIB_PATH = os.environ.get("CDUGKS_LIBRARY") or os.path.join(HERE, "libcdugks.so")
 
 OK, PENDING = 0, 1
 ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_NONPHYSICAL, ERR_TOO_LARGE, ERR_BUSY, ERR_UNKNOWN = -1, -2, -3, -4, -5, -6, -7

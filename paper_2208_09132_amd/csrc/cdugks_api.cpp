@@ -192,10 +192,16 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
     // byte plan
     const size_t es = r.storage == CDUGKS_STORE_F64 ? 8 : 4;
     const size_t NV = (size_t)r.N * r.V;
+    // Consecutive regions are staggered by 4.25 KB each: arrays read at the
+    // same element index (g, b, the quarter-step fields, the face values)
+    // would otherwise sit at offsets that are multiples of a large power of
+    // two whenever their sizes are (the 3-D workload: 2^32 bytes each), and
+    // contend for the same memory channels.
+    constexpr size_t STAGGER = 4352;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
-        off += align_up(bytes);
+        off += align_up(bytes) + (bytes >= (1u << 20) ? STAGGER : 0);
         return o;
     };
     for (int k = 0; k < 2; ++k) {
@@ -204,8 +210,11 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
         r.off_W[k] = take((size_t)(D + 2) * r.N * 8);
         r.off_P[k] = take((size_t)NPC * r.N * 8);
     }
-    r.off_q = quarter_stored(D) ? take(2 * NV * es) : 0;
-    r.off_FV = take((size_t)D * 2 * r.V * r.NE * es);
+    r.off_q[0] = quarter_stored(D) ? take(NV * es) : 0;
+    r.off_q[1] = quarter_stored(D) ? take(NV * es) : 0;
+    // face values: 2D blocks of V NE values, each block padded by the stagger
+    r.fv_stride = (long long)r.V * r.NE + (long long)(STAGGER / es);
+    r.off_FV = take((size_t)D * 2 * (size_t)r.fv_stride * es);
     r.off_FS = take((size_t)r.nslices * D * (2 * D + 3) * r.NE * 8);
     r.off_FP = take((size_t)D * NFP * r.NE * 8);
     r.off_G = take((size_t)D * (D + 2) * r.NE * 8);
@@ -329,10 +338,11 @@ void fill_problem(const Resolved& r, char* base, Problem& P) {
     P.axis_xi = (const double*)(base + r.off_axis);
     P.axis_w = P.axis_xi + (r.nv[0] + r.nv[1] + r.nv[2]);
     if (quarter_stored(r.D)) {
-        P.qg = base + r.off_q;
-        P.qb = base + r.off_q + (size_t)r.N * r.V * (r.storage == CDUGKS_STORE_F64 ? 8 : 4);
+        P.qg = base + r.off_q[0];
+        P.qb = base + r.off_q[1];
     }
     P.FV = base + r.off_FV;
+    P.fv_stride = r.fv_stride;
     P.FS = (double*)(base + r.off_FS);
     P.FP = (double*)(base + r.off_FP);
     P.G = (double*)(base + r.off_G);

@@ -25,8 +25,9 @@ struct Resolved {
     double dt, gamma, Pr, R, omega, K, c_int, mu_ref, T_ref, tau_inv;
     // byte offsets inside the problem's device block
     size_t off_g[2], off_b[2], off_W[2], off_P[2];
-    size_t off_q, off_FV, off_FS, off_FP, off_G, off_vel, off_axis, off_err, off_scratch;
+    size_t off_q[2], off_FV, off_FS, off_FP, off_G, off_vel, off_axis, off_err, off_scratch;
     size_t bytes;
+    long long fv_stride;  // elements between the (d, field) blocks of the face values
 };
 
 // Steps per captured graph of a single context.

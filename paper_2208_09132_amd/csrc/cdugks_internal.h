@@ -66,7 +66,8 @@ struct Problem {
     const double* P_in; double* P_out;
     void* qg;     // quarter-step fields [V][N] for g and b, storage precision
     void* qb;     // (null unless quarter_stored(D))
-    void* FV;     // face values phi_bar [D][2][V][NE], storage precision
+    void* FV;     // face values phi_bar [D][2][fv_stride], block (d, field) holds [V][NE]
+    long long fv_stride;  // >= V NE (padded so the blocks do not alias)
     double* FS;   // face partial sums [nslices][D][2D+3][NE]
     double* FP;   // face coefficients [D][NFP][NE]
     double* G;    // flux moments [D][D+2][NE]

@@ -362,6 +362,21 @@ __device__ __forceinline__ void face_pair(const CT* const* sq, const CT* const* 
     }
 }
 
+// The same face value from explicit stencil values: q and slopes a_e at the
+// upwind cell u, slopes at u - d (aL) and u + d (aR).
+template <int D, typename CT>
+__device__ __forceinline__ CT face_value_at(CT qU, const CT* aU, const CT* aL, const CT* aR, int d, CT s,
+                                            const Vel& v) {
+    const CT half = CT(0.5);
+    CT val = qU + half * s * aU[d];
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        CT bde = van_leer(aU[e] - aL[e], aR[e] - aU[e]);
+        val -= CT(v.lam[e]) * (aU[e] + half * s * bde);
+    }
+    return val;
+}
+
 // Face coefficients used to invert eq. phibar at a face: NFC per face.
 template <int D>
 struct FaceCoef {
@@ -479,45 +494,44 @@ struct FaceSumKernel {
     static constexpr int NHALO = G::NQ - NT;
     static constexpr int NSLOT = 1 + (NHALO + WG - 1) / WG;
 
-    // Box index of the h-th halo point of the q box in box order (interior
-    // points skipped): planes below the interior in z are full, the interior
-    // planes miss the tile's TX x TY block, and likewise rows within a plane.
-    __device__ static int halo_point(int h) {
-        constexpr int QX = G::QX, QY = G::QY, QZ = G::QZ;
-        constexpr int PL = QX * QY;                 // points per full plane
-        constexpr int PI = PL - G::TX * G::TY;      // halo points per interior plane
-        constexpr int RI = QX - G::TX;              // halo points per interior row
-        int z, rem;
-        if (h < G::OQZ * PL) {
-            z = h / PL;
-            return h;  // below the interior: box order equals halo order
-        }
-        h -= G::OQZ * PL;
-        if (h >= G::TZ * PI) {
-            h -= G::TZ * PI;
-            return (G::OQZ + G::TZ) * PL + h;  // above the interior
-        }
-        z = G::OQZ + h / PI;
-        rem = h % PI;
-        int y, x;
-        if (rem < G::OQY * QX) {
-            y = rem / QX;
-            x = rem % QX;
+    // Box index of the h-th point of a box (extents BX, BY, BZ; the tile sits
+    // at offsets OX, OY, OZ) that lies outside the tile, in box order: planes
+    // below the tile in z are full, the tile's planes miss its TX x TY block,
+    // and likewise rows within a plane.
+    template <int BX, int BY, int OX, int OY, int OZ>
+    __device__ static int ring_point(int h) {
+        constexpr int PL = BX * BY;                 // points per full plane
+        constexpr int PI = PL - G::TX * G::TY;      // ring points per tile plane
+        constexpr int RI = BX - G::TX;              // ring points per tile row
+        if (h < OZ * PL) return h;  // below the tile: box order equals ring order
+        h -= OZ * PL;
+        if (h >= G::TZ * PI) return (OZ + G::TZ) * PL + (h - G::TZ * PI);  // above
+        const int z = OZ + h / PI;
+        int rem = h % PI, y, x;
+        if (rem < OY * BX) {
+            y = rem / BX;
+            x = rem % BX;
         } else {
-            rem -= G::OQY * QX;
+            rem -= OY * BX;
             if (rem >= G::TY * RI) {
                 rem -= G::TY * RI;
-                y = G::OQY + G::TY + rem / QX;
-                x = rem % QX;
+                y = OY + G::TY + rem / BX;
+                x = rem % BX;
             } else {
-                y = G::OQY + rem / RI;
-                int c = rem % RI;
-                x = c < G::OQX ? c : c + G::TX;
+                y = OY + rem / RI;
+                const int c = rem % RI;
+                x = c < OX ? c : c + G::TX;
             }
         }
-        (void)QZ;
-        return x + QX * (y + QY * z);
+        return x + BX * (y + BY * z);
     }
+    __device__ static int halo_point(int h) { return ring_point<G::QX, G::QY, G::OQX, G::OQY, G::OQZ>(h); }
+    __device__ static int slope_ring_point(int h) {
+        return ring_point<G::AX, G::AY, G::OAX, G::OAY, G::OAZ>(h);
+    }
+    // slope-box points outside the tile, and passes over them
+    static constexpr int NARING = G::NA - NT;
+    static constexpr int NRING = (NARING + WG - 1) / WG;
 
     // when the q-box points do not fit in registers, the cell coefficients
     // of the whole box are staged in LDS once (3-D FP32; the FP64 3-D box does
@@ -619,21 +633,25 @@ struct FaceSumKernel {
 #pragma unroll
             for (int j = 0; j < NS; ++j) acc[d][j] = 0.0;
 
-        // software pipelining: the next velocity's g, b are loaded while the
-        // current one is processed (when the q-box slots fit in registers)
+        // Software pipelining: the next velocity's fields are loaded while the
+        // current one is processed (when the q-box slots fit in registers).
+        // The loop is unrolled by two over two named register sets, so a
+        // register with a load in flight is never copied: a copy would make
+        // the compiler wait for every outstanding memory operation, the face
+        // value stores included.
         constexpr bool PREFETCH = NSLOT <= 2 || QS;
-        const void* const src_g = QS ? P.qg : P.g_in;
-        const void* const src_b = QS ? P.qb : P.b_in;
-        double pg[NSLOT], pbv[NSLOT];
+        const ST* const src_g = reinterpret_cast<const ST*>(QS ? P.qg : P.g_in);
+        const ST* const src_b = reinterpret_cast<const ST*>(QS ? P.qb : P.b_in);
+        ST pa_g[NSLOT], pa_b[NSLOT], pb_g[NSLOT], pb_b[NSLOT];
         if constexpr (PREFETCH) {
 #pragma unroll
             for (int k = 0; k < NSLOT; ++k) {
                 const long long a0 = (long long)(v0 < v1 ? v0 : 0) * N + srcq[k];
-                pg[k] = ld<ST>(src_g, a0);
-                pbv[k] = ld<ST>(src_b, a0);
+                pa_g[k] = src_g[a0];
+                pa_b[k] = src_b[a0];
             }
         }
-        const long long fstride = (long long)P.V * NE;  // per (d, field) block of FV
+        const long long fstride = P.fv_stride;  // per (d, field) block of FV
 
         // Maxwellians of the q-box slots by recurrence along velocity axis 0
         // (when the slot coefficients live in registers)
@@ -647,7 +665,9 @@ struct FaceSumKernel {
         }
         int ix = v0 % nvx;
 
-        for (int i = v0; i < v1; ++i) {
+        // one velocity: cur_* hold its prefetched fields, nxt_* receive the next
+        auto velocity = [&](int i, int buf, ST(&cur_g)[NSLOT], ST(&cur_b)[NSLOT], ST(&nxt_g)[NSLOT],
+                            ST(&nxt_b)[NSLOT]) __attribute__((always_inline)) {
             const Vel v = load_vel(P.vel, i);
             if constexpr (WALKER) {
                 if (i == v0 || ix % WALK == 0) {
@@ -661,24 +681,19 @@ struct FaceSumKernel {
                 }
             }
             const long long vb = (long long)i * N;
-            const int buf = NBUF == 2 ? ((i - v0) & 1) : 0;
             CT* const sq0 = sm.q[buf][0];
             CT* const sq1 = sm.q[buf][1];
             CT* const sa0 = sm.a[buf][0];
             CT* const sa1 = sm.a[buf][1];
-            const CT* sqp[2] = {sq0, sq1};
-            const CT* sap[2] = {sa0, sa1};
-            double cg[NSLOT], cbv[NSLOT];
+            CT q_own[2], a_own[2][D];  // the own cell's q and slopes
             if constexpr (PREFETCH) {
                 // unconditional loads (the last velocity re-reads itself) keep
                 // the wait counts exact
                 const long long nb = i + 1 < v1 ? vb + N : vb;
 #pragma unroll
                 for (int k = 0; k < NSLOT; ++k) {
-                    cg[k] = pg[k];
-                    cbv[k] = pbv[k];
-                    pg[k] = ld<ST>(src_g, nb + srcq[k]);
-                    pbv[k] = ld<ST>(src_b, nb + srcq[k]);
+                    nxt_g[k] = src_g[nb + srcq[k]];
+                    nxt_b[k] = src_b[nb + srcq[k]];
                 }
             }
 
@@ -689,11 +704,11 @@ struct FaceSumKernel {
                 if (r >= 0) {
                     double g, b;
                     if constexpr (PREFETCH) {
-                        g = cg[k];
-                        b = cbv[k];
+                        g = (double)cur_g[k];
+                        b = (double)cur_b[k];
                     } else {
-                        g = ld<ST>(src_g, vb + srcq[k]);
-                        b = ld<ST>(src_b, vb + srcq[k]);
+                        g = (double)src_g[vb + srcq[k]];
+                        b = (double)src_b[vb + srcq[k]];
                     }
                     double qg, qb;
                     if constexpr (QS) {
@@ -716,24 +731,45 @@ struct FaceSumKernel {
                     }
                     sq0[r] = CT(qg);
                     sq1[r] = CT(qb);
+                    if (k == 0) {  // slot 0 is the own cell
+                        q_own[0] = CT(qg);
+                        q_own[1] = CT(qb);
+                    }
                 }
             }
             __syncthreads();
 
-            // stage 2: limited differences on the slope box
+            // stage 2: limited differences on the slope box; the own cell first
+            // (its values stay in registers for stage 3), then the ring
+            {
+                const int ai = G::aidx(tx, ty, tz), qi = G::qidx(tx, ty, tz);
 #pragma unroll
-            for (int k = 0; k < G::NRA; ++k) {
-                int p = tid + k * WG;
-                if (p < G::NA) {
-                    int px = p % G::AX, py = (p / G::AX) % G::AY, pz = p / (G::AX * G::AY);
-                    int qi = (px + 1) + G::QX * ((py + (D >= 2 ? 1 : 0)) + G::QY * (pz + (D >= 3 ? 1 : 0)));
+                for (int e = 0; e < D; ++e) {
+                    const int sq = G::SQ(e);
+#pragma unroll
+                    for (int f = 0; f < 2; ++f) {
+                        const CT* q = f == 0 ? sq0 : sq1;
+                        const CT c = q_own[f];
+                        const CT a = van_leer(c - q[qi - sq], q[qi + sq] - c);
+                        (f == 0 ? sa0 : sa1)[e * G::NA + ai] = a;
+                        a_own[f][e] = a;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NRING; ++k) {
+                const int h = tid + k * WG;
+                if (h < NARING) {
+                    const int p = slope_ring_point(h);
+                    const int px = p % G::AX, py = (p / G::AX) % G::AY, pz = p / (G::AX * G::AY);
+                    const int qi = (px + 1) + G::QX * ((py + (D >= 2 ? 1 : 0)) + G::QY * (pz + (D >= 3 ? 1 : 0)));
 #pragma unroll
                     for (int e = 0; e < D; ++e) {
-                        int sq = G::SQ(e);
+                        const int sq = G::SQ(e);
 #pragma unroll
                         for (int f = 0; f < 2; ++f) {
                             const CT* q = f == 0 ? sq0 : sq1;
-                            CT c = q[qi];
+                            const CT c = q[qi];
                             (f == 0 ? sa0 : sa1)[e * G::NA + p] = van_leer(c - q[qi - sq], q[qi + sq] - c);
                         }
                     }
@@ -741,15 +777,45 @@ struct FaceSumKernel {
             }
             __syncthreads();
 
-            // stage 3: left face of the own cell along each d
+            // stage 3: left face of the own cell along each d.  Upwind cell u
+            // is c - d (xi_d > 0) or c (xi_d < 0); the own cell's q and slopes
+            // come from registers, the others from LDS.
 #pragma unroll
             for (int d = 0; d < D; ++d) {
-                int dxo = d == 0, dyo = d == 1, dzo = d == 2;
-                CT vgc, vbc;
-                face_pair<D, G, CT>(sqp, sap, d, G::qidx(tx - dxo, ty - dyo, tz - dzo),
-                                    G::aidx(tx - dxo, ty - dyo, tz - dzo), G::qidx(tx, ty, tz),
-                                    G::aidx(tx, ty, tz), v, vgc, vbc);
-                const double vg = vgc, vb2 = vbc;
+                const int dxo = d == 0, dyo = d == 1, dzo = d == 2;
+                const double xd = d == 0 ? v.xi[0] : (d == 1 ? v.xi[1] : v.xi[2]);
+                const int q_m = G::qidx(tx - dxo, ty - dyo, tz - dzo);
+                const int a_m = G::aidx(tx - dxo, ty - dyo, tz - dzo);
+                const int a_mm = G::aidx(tx - 2 * dxo, ty - 2 * dyo, tz - 2 * dzo);
+                const int a_p = G::aidx(tx + dxo, ty + dyo, tz + dzo);
+                CT fv[2];
+#pragma unroll
+                for (int f = 0; f < 2; ++f) {
+                    const CT* sq = f == 0 ? sq0 : sq1;
+                    const CT* sa = f == 0 ? sa0 : sa1;
+                    CT aU[D], aL[D], aR[D];
+                    CT left = 0, right = 0;
+                    if (xd >= 0.0) {  // upwind c - d: its left and right neighbours are c - 2d and c
+#pragma unroll
+                        for (int e = 0; e < D; ++e) {
+                            aU[e] = sa[e * G::NA + a_m];
+                            aL[e] = sa[e * G::NA + a_mm];
+                            aR[e] = a_own[f][e];
+                        }
+                        left = face_value_at<D, CT>(sq[q_m], aU, aL, aR, d, CT(1), v);
+                    }
+                    if (xd <= 0.0) {  // upwind c: neighbours c - d and c + d
+#pragma unroll
+                        for (int e = 0; e < D; ++e) {
+                            aU[e] = a_own[f][e];
+                            aL[e] = sa[e * G::NA + a_m];
+                            aR[e] = sa[e * G::NA + a_p];
+                        }
+                        right = face_value_at<D, CT>(q_own[f], aU, aL, aR, d, CT(-1), v);
+                    }
+                    fv[f] = xd > 0.0 ? left : (xd < 0.0 ? right : CT(0.5) * (left + right));
+                }
+                const double vg = fv[0], vb2 = fv[1];
                 if (fvalid[d]) {
                     const long long o = (long long)(2 * d) * fstride + (long long)i * NE + fe;
                     st_stream<ST>(P.FV, o, vg);
@@ -775,6 +841,26 @@ struct FaceSumKernel {
             // velocity writes the other buffer, and the one after that comes
             // only after two more barriers
             if constexpr (NBUF == 1) __syncthreads();
+        };
+
+        if constexpr (D <= 2) {
+            int i = v0;
+            for (; i + 1 < v1; i += 2) {
+                velocity(i, 0, pa_g, pa_b, pb_g, pb_b);
+                velocity(i + 1, NBUF - 1, pb_g, pb_b, pa_g, pa_b);
+            }
+            if (i < v1) velocity(i, 0, pa_g, pa_b, pb_g, pb_b);
+        } else {
+            // 3-D: registers allow one set; the copy costs a wait per velocity
+            for (int i = v0; i < v1; ++i) {
+                ST cg[NSLOT], cb[NSLOT];
+#pragma unroll
+                for (int k = 0; k < NSLOT; ++k) {
+                    cg[k] = pa_g[k];
+                    cb[k] = pa_b[k];
+                }
+                velocity(i, 0, cg, cb, pa_g, pa_b);
+            }
         }
 
         // partial face sums of this velocity slice
@@ -831,7 +917,7 @@ struct UpdateKernel {
         }
         const int v0 = (int)((long long)P.V * slice / nslices);
         const int v1 = (int)((long long)P.V * (slice + 1) / nslices);
-        const long long fstride = (long long)P.V * NE;
+        const long long fstride = P.fv_stride;
         const double dt = P.dt;
         // constant parts of eq. phiupdate
         const double inv_g = 1.0 / (1.0 + 2.0 * k1.beta), inv_b = 1.0 / (1.0 + 2.0 * k1.betab);
@@ -940,8 +1026,13 @@ struct UpdateKernel {
     }
 };
 
+// waves per SIMD the face-sum kernel is compiled for (register budget; 3-D
+// takes what it needs)
+template <int D>
+constexpr int face_sum_waves() { return D == 1 ? 4 : (D == 2 ? 3 : 1); }
+
 template <int D, typename ST>
-__global__ __launch_bounds__(WG) void k_face_sums(Problem P) {
+__global__ __launch_bounds__(WG, face_sum_waves<D>()) void k_face_sums(Problem P) {
     using K = FaceSumKernel<D, ST>;
     __shared__ typename K::Smem sm;
     int ntiles = P.tiles1[0] * P.tiles1[1] * P.tiles1[2];
