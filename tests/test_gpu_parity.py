@@ -86,6 +86,41 @@ def test_3d_small_fp64():
     check_parity(q, 4, 1e-12)
 
 
+def test_3d_workload_velocity_grid_fp32():
+    """The 3-D shear workload's 16^3 velocity grid on 16^3 cells (several
+    tiles per axis), FP32 storage, Kn = 1e-3 and 1e-1, against the oracle."""
+    p = wl.shear3d(n=16, nv=16, Kn=1e-3, storage="f32")
+    check_parity(p, 30, 1e-5)
+    q = wl.shear3d(n=16, nv=16, Kn=1e-1, storage="f32")
+    check_parity(q, 10, 1e-5)
+
+
+def test_3d_full_size_fp32_conservation_and_stationarity():
+    """The 3-D workload at full size (64^3 cells x 16^3 velocities, FP32
+    storage, the launch configuration the benchmark times): totals conserved
+    to round-off; a uniform moving state leaves W bitwise unchanged."""
+    p = wl.shear3d(storage="f32")
+    _log("3-D full size: conservation")
+    s = cd.Solver(p)
+    W0 = s.conserved().sum(axis=0)
+    s.step(3)
+    W1 = s.conserved().sum(axis=0)
+    s.close()
+    assert np.max(np.abs(W1 - W0)) <= 1e-13 * np.max(np.abs(W0)) * math.sqrt(3) * 10
+    u = dict(p)
+    N = 64 ** 3
+    u["rho"] = np.full(N, 1.2)
+    u["T"] = np.full(N, 0.8)
+    u["u"] = np.stack([np.full(N, 0.2), np.full(N, -0.1), np.full(N, 0.05)])
+    _log("3-D full size: stationarity")
+    s = cd.Solver(u)
+    Wa = s.conserved()
+    s.step(2)
+    Wb = s.conserved()
+    s.close()
+    assert np.array_equal(Wa, Wb)
+
+
 def test_fp32_storage_within_1e5():
     p = wl.kelvin_helmholtz(n=40, nv=12, storage="f32")
     check_parity(p, 20, 1e-5)
