@@ -112,7 +112,9 @@ int cdugks_required_bytes(const cdugks_space* space, const cdugks_velocity* vel,
  * the library allocates.  Validation failures return CDUGKS_ERR_INVALID:
  * dim outside 1..3, n < 1, nv < 2, Boole with nv != 4k+1, gamma outside
  * (1, 5/3], Pr <= 0, R <= 0, rho <= 0, T <= 0, a requested dt above the CFL
- * bound.  Returns after enqueueing the initialisation. */
+ * bound, and sizes beyond the kernels' index ranges (faces >= 2^31,
+ * velocities >= 2^24, cells x velocities > 2^40; cdugks_required_bytes
+ * rejects these too).  Returns after enqueueing the initialisation. */
 int cdugks_init(const cdugks_space* space, const cdugks_velocity* vel,
                 const cdugks_params* params, const double* rho, const double* u,
                 const double* T, void* hip_stream, void* arena, size_t arena_bytes,

@@ -85,6 +85,19 @@ def test_validation_rejects_nonphysical_moments():
         cd.cdugks_init(p)
 
 
+def test_sizes_beyond_the_index_ranges_are_rejected():
+    """Faces >= 2^31 or cells x velocities > 2^40 exceed the kernels' index
+    arithmetic: refused before any allocation (the arrays here are never
+    built; only the description is)."""
+    for n, nv in (([1 << 16, 1 << 16], [4, 4]), ([1 << 12, 1 << 12], [1024, 1024])):
+        p = {"dim": 2, "n": n, "lo": [0.0, 0.0], "hi": [1.0, 1.0], "bc": ["periodic", "periodic"],
+             "nv": nv, "vmin": [-6.0, -6.0], "vmax": [6.0, 6.0], "relax": "mu", "mu_ref": 1e-3}
+        with pytest.raises(cd.CdugksError) as ei:
+            cd.cdugks_required_bytes(p)
+        assert ei.value.code == cd.ERR_INVALID
+        assert "too large" in str(ei.value)
+
+
 def test_null_context_is_rejected():
     lib = cd.load_library()
     assert lib.cdugks_step(None, 1) == cd.ERR_INVALID
