@@ -291,7 +291,7 @@ void velocity_tables(const Resolved& r, std::vector<double>& vel, std::vector<do
             v[VE_XI0 + d] = x;
             w *= wts[d][m[d]];
             x2 += x * x;
-            v[VE_LAM0 + d] = 0.5 * r.dt * x / r.dx[d];
+            v[VE_LAM0 + d] = r.dt * x / r.dx[d];  // twice (dt/2) xi_d / dx_d
         }
         v[VE_W] = w;
         v[VE_HX2] = 0.5 * x2;

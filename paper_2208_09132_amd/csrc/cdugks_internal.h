@@ -25,8 +25,9 @@ enum { PC_A = 0, PC_INV2RT, PC_CRT2, PC_BETA, PC_BETAB, PC_ETA, PC_HU2, PC_U0, N
 enum { PF_A = 0, PF_INV2RT, PF_CRT2, PF_IG, PF_BG, PF_IB, PF_BB, PF_EB, PF_HU2, PF_U0,
        NFP = PF_U0 + 3 };
 
-// Per-velocity constants ([V][NVEL]): xi, weight, |xi|^2/2, the Courant-like
-// numbers lambda_d = (dt/2) xi_d / dx_d, and the weighted products used by the
+// Per-velocity constants ([V][NVEL]): xi, weight, |xi|^2/2, twice the
+// Courant-like numbers, 2 lambda_d = dt xi_d / dx_d (the face value is
+// assembled from half-scale slopes), and the weighted products used by the
 // face sums, w xi_e and w xi_d xi_e ([d][e], 3 x 3).
 enum { VE_XI0 = 0, VE_W = 3, VE_HX2 = 4, VE_LAM0 = 5, VE_WXI0 = 8, VE_WXX = 11, NVEL = 20 };
 

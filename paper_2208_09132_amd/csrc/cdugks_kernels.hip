@@ -52,24 +52,30 @@ __device__ __forceinline__ double rcp_nr(double s) {
     return fma(r, fma(-s, r, 1.0), r);
 }
 
-// Van Leer limiter (eq. VanLeer) in the harmonic-mean form: identical to
-// (sgn a + sgn b)|a||b|/(|a|+|b|); zero at extrema and for a flat side.
-// When a b > 0 the sum a + b is nonzero, so the reciprocal is safe; otherwise
+// Van Leer limiter (eq. VanLeer) at half scale: H(a, b) = ab/(a + b) when
+// ab > 0, else 0, which is half the harmonic-mean form 2ab/(a+b) =
+// (sgn a + sgn b)|a||b|/(|a|+|b|): zero at extrema and for a flat side.  The
+// kernels carry every limited slope at half scale (and slopes of slopes at a
+// quarter), folding the factors into the Courant numbers; all the scalings
+// are powers of two, so the values are those of the full-scale form exactly
+// (except where a product is subnormal, as in the far velocity tails of the
+// FP32 form).
+// When ab > 0 the sum a + b is nonzero, so the reciprocal is safe; otherwise
 // its value is discarded by the select.
-__device__ __forceinline__ double van_leer(double a, double b) {
+__device__ __forceinline__ double half_van_leer(double a, double b) {
     double p = a * b;
-    double v = (p + p) * rcp_nr(a + b);
+    double v = p * rcp_nr(a + b);
     return p > 0.0 ? v : 0.0;
 }
 
-// FP32 form of the limiter for the FP32-storage stencil: the hardware
-// reciprocal plus one Newton step.
-__device__ __forceinline__ float van_leer(float a, float b) {
+// FP32 form for the FP32-storage stencil: the hardware reciprocal plus one
+// Newton step.
+__device__ __forceinline__ float half_van_leer(float a, float b) {
     float p = a * b;
     float s = a + b;
     float r = __builtin_amdgcn_rcpf(s);
     r = fmaf(r, fmaf(-s, r, 1.0f), r);
-    float v = (p + p) * r;
+    float v = p * r;
     return p > 0.0f ? v : 0.0f;
 }
 
@@ -249,7 +255,7 @@ __device__ __forceinline__ CellCoef load_coef(const double* Pc, long long N, lon
 }
 
 struct Vel {
-    double xi[3], w, hx2, lam[3];
+    double xi[3], w, hx2, lam2[3];
 };
 
 // The velocity table is read-only for the whole launch: reading it through the
@@ -266,7 +272,7 @@ __device__ __forceinline__ Vel load_vel(const double* vel, int i) {
     Vel r;
     r.xi[0] = v[0]; r.xi[1] = v[1]; r.xi[2] = v[2];
     r.w = v[VE_W]; r.hx2 = v[VE_HX2];
-    r.lam[0] = v[VE_LAM0]; r.lam[1] = v[VE_LAM0 + 1]; r.lam[2] = v[VE_LAM0 + 2];
+    r.lam2[0] = v[VE_LAM0]; r.lam2[1] = v[VE_LAM0 + 1]; r.lam2[2] = v[VE_LAM0 + 2];
     return r;
 }
 
@@ -320,59 +326,22 @@ __global__ __launch_bounds__(256) void k_init_quarter(Problem P) {
     st<ST>(P.qb, idx, qb);
 }
 
-// Value of phi_bar at a face centre at t_{n+1/2}: upwind cell u (LDS indices
-// qi, ai), side s = +1 when the face is u's right face, -1 when its left face.
+// Value of phi_bar at a face centre at t_{n+1/2} from the upwind cell u,
+// side s = +1 when the face is u's right face, -1 when its left face:
 //   v = q(u) + s a_d/2 - sum_e lambda_e (a_e + s b_de/2),
 // a_e = VL of one-sided differences of q along e (slope times dx_e) and
 // b_de = VL of differences of a_e along d (slope of the slope times dx_d dx_e).
-template <int D, class GEO, typename CT>
-__device__ __forceinline__ CT face_value(const CT* sq, const CT* sa, int d, int qi, int ai, CT s,
-                                         const Vel& v) {
-    const int sd = GEO::SA(d);
-    const CT half = CT(0.5);
-    CT val = sq[qi] + half * s * sa[d * GEO::NA + ai];
-#pragma unroll
-    for (int e = 0; e < D; ++e) {
-        const CT* ae = sa + e * GEO::NA;
-        CT a0 = ae[ai];
-        CT bde = van_leer(a0 - ae[ai - sd], ae[ai + sd] - a0);
-        val -= CT(v.lam[e]) * (a0 + half * s * bde);
-    }
-    return val;
-}
-
-// Both one-sided candidates of a face: left upwind cell (qi_l, ai_l) used when
-// xi_d > 0, right upwind cell (qi_r, ai_r) when xi_d < 0, their mean at xi_d = 0.
-template <int D, class GEO, typename CT>
-__device__ __forceinline__ void face_pair(const CT* const* sq, const CT* const* sa, int d, int qi_l, int ai_l,
-                                          int qi_r, int ai_r, const Vel& v, CT& vg, CT& vb) {
-    const double xd = d == 0 ? v.xi[0] : (d == 1 ? v.xi[1] : v.xi[2]);
-    if (xd != 0.0) {
-        const bool pos = xd > 0.0;
-        const int qi = pos ? qi_l : qi_r, ai = pos ? ai_l : ai_r;
-        const CT s = pos ? CT(1) : CT(-1);
-        vg = face_value<D, GEO, CT>(sq[0], sa[0], d, qi, ai, s, v);
-        vb = face_value<D, GEO, CT>(sq[1], sa[1], d, qi, ai, s, v);
-    } else {
-        const CT half = CT(0.5);
-        vg = half * (face_value<D, GEO, CT>(sq[0], sa[0], d, qi_l, ai_l, CT(1), v) +
-                     face_value<D, GEO, CT>(sq[0], sa[0], d, qi_r, ai_r, CT(-1), v));
-        vb = half * (face_value<D, GEO, CT>(sq[1], sa[1], d, qi_l, ai_l, CT(1), v) +
-                     face_value<D, GEO, CT>(sq[1], sa[1], d, qi_r, ai_r, CT(-1), v));
-    }
-}
-
-// The same face value from explicit stencil values: q and slopes a_e at the
-// upwind cell u, slopes at u - d (aL) and u + d (aR).
+// Arguments at the scales the kernels carry: ha = a/2 at u (haU) and at
+// u - d (haL), u + d (haR); lam2 = 2 lambda.  Then
+//   v = q(u) + s ha_d - sum_e lam2_e (ha_e + s hb_de),  hb_de = b_de/4 = H(ha differences).
 template <int D, typename CT>
-__device__ __forceinline__ CT face_value_at(CT qU, const CT* aU, const CT* aL, const CT* aR, int d, CT s,
+__device__ __forceinline__ CT face_value_at(CT qU, const CT* haU, const CT* haL, const CT* haR, int d, CT s,
                                             const Vel& v) {
-    const CT half = CT(0.5);
-    CT val = qU + half * s * aU[d];
+    CT val = qU + s * haU[d];
 #pragma unroll
     for (int e = 0; e < D; ++e) {
-        CT bde = van_leer(aU[e] - aL[e], aR[e] - aU[e]);
-        val -= CT(v.lam[e]) * (aU[e] + half * s * bde);
+        CT hb = half_van_leer(haU[e] - haL[e], haR[e] - haU[e]);
+        val -= CT(v.lam2[e]) * (haU[e] + s * hb);
     }
     return val;
 }
@@ -750,7 +719,7 @@ struct FaceSumKernel {
                     for (int f = 0; f < 2; ++f) {
                         const CT* q = f == 0 ? sq0 : sq1;
                         const CT c = q_own[f];
-                        const CT a = van_leer(c - q[qi - sq], q[qi + sq] - c);
+                        const CT a = half_van_leer(c - q[qi - sq], q[qi + sq] - c);
                         (f == 0 ? sa0 : sa1)[e * G::NA + ai] = a;
                         a_own[f][e] = a;
                     }
@@ -770,7 +739,7 @@ struct FaceSumKernel {
                         for (int f = 0; f < 2; ++f) {
                             const CT* q = f == 0 ? sq0 : sq1;
                             const CT c = q[qi];
-                            (f == 0 ? sa0 : sa1)[e * G::NA + p] = van_leer(c - q[qi - sq], q[qi + sq] - c);
+                            (f == 0 ? sa0 : sa1)[e * G::NA + p] = half_van_leer(c - q[qi - sq], q[qi + sq] - c);
                         }
                     }
                 }
