@@ -144,6 +144,7 @@ def served_run(nreq: int, budget_gb: float = 200.0, max_active: int = 64, chunk:
         upd += int(np.prod(p["n"])) * int(np.prod(p["nv"])) * p["steps"]
     lat, qs, ss = [], [], []
     pending = dict(tickets)
+    last = time.perf_counter()
     while pending:
         for t in list(pending):
             r = srv.poll(t)
@@ -153,6 +154,9 @@ def served_run(nreq: int, budget_gb: float = 200.0, max_active: int = 64, chunk:
                 ss.append(ts)
                 lat.append(tq + ts)
                 del pending[t]
+        if time.perf_counter() - last > 30.0:  # progress for long streams
+            last = time.perf_counter()
+            print(f"served: {nreq - len(pending)}/{nreq} done after {last - t0:.0f} s", file=sys.stderr, flush=True)
         time.sleep(0.002)
     makespan = time.perf_counter() - t0
     srv.close()
