@@ -96,14 +96,15 @@ hipError_t launch_moments(const Problem& P, const double* W, double* rho, double
 hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStream_t s);
 
 // Batched: one launch per phase across problems of one storage class.  The
-// tile-kernel launches are persistent (grid = resident slots, each workgroup
-// strides over the work list); maxd is the largest dimension in the class.
-// The per-face and per-cell closures take per-problem prefix offsets (in
-// threads).
+// tile-kernel launches are persistent (grid = resident slots; workgroups take
+// items from the device counter `queue`, which must be 0 at launch, and reset
+// the counter `other` of the other kernel of the pair); maxd is the largest
+// dimension in the class.  The per-face and per-cell closures take
+// per-problem prefix offsets (in threads).
 hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int grid,
-                                    int maxd, int storage, hipStream_t s);
+                                    int maxd, int storage, int* queue, int* other, hipStream_t s);
 hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, int nitems, int grid, int maxd,
-                                 int storage, hipStream_t s);
+                                 int storage, int* queue, int* other, hipStream_t s);
 int batched_blocks_per_cu(int maxd, int storage, bool update);
 hipError_t launch_face_close_batched(const Problem* probs, const long long* offsets, int nprob,
                                      long long total, hipStream_t s);

@@ -1010,18 +1010,33 @@ __global__ __launch_bounds__(WG, face_sum_waves<D>()) void k_face_sums(Problem P
 }
 
 // Batched face sums: one launch for every tile of every problem of a storage
-// class.  Persistent: the grid covers the resident slots and each workgroup
-// walks the (cost-sorted) work list with a fixed stride, so the assignment of
-// work to workgroups never depends on timing.  Problems of different
-// dimension share the launch; LDS is the union of their needs.
+// class.  Persistent: the grid covers the resident slots and the workgroups
+// take (cost-sorted, largest first) items from a device queue: an atomic
+// counter, so a workgroup that finishes early takes the next item.  Which
+// workgroup computes an item does not change its result.  The launch resets
+// the other kernel's counter (that kernel's previous launch has finished and
+// its next one starts after this one), so no memset enters a graph.
+// Problems of different dimension share the launch; LDS is the union of their
+// needs.
+__device__ __forceinline__ int next_item(int* queue, int* slot) {
+    if (threadIdx.x == 0) *slot = atomicAdd(queue, 1);
+    __syncthreads();
+    const int w = *slot;
+    __syncthreads();  // every thread has read the slot before it is refilled
+    return w;
+}
+
 template <typename ST, int MAXD>
-__global__ __launch_bounds__(WG) void k_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems) {
+__global__ __launch_bounds__(WG) void k_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems,
+                                                          int* queue, int* other) {
     __shared__ union U {
         typename FaceSumKernel<1, ST>::Smem s1;
         typename FaceSumKernel<MAXD >= 2 ? 2 : 1, ST>::Smem s2;
         typename FaceSumKernel<MAXD >= 3 ? 3 : 1, ST>::Smem s3;
     } sm;
-    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    __shared__ int slot;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *other = 0;
+    for (int w = next_item(queue, &slot); w < nitems; w = next_item(queue, &slot)) {
         const WorkItem it = items[w];
         const Problem P = probs[it.prob];
         if (P.D == 1) FaceSumKernel<1, ST>::run(P, it.tile, it.slice, P.nslices, sm.s1);
@@ -1042,8 +1057,11 @@ __global__ __launch_bounds__(WG, 2) void k_update(Problem P) {
 }
 
 template <typename ST, int MAXD>
-__global__ __launch_bounds__(WG) void k_update_batched(const Problem* probs, const WorkItem* items, int nitems) {
-    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+__global__ __launch_bounds__(WG) void k_update_batched(const Problem* probs, const WorkItem* items, int nitems,
+                                                       int* queue, int* other) {
+    __shared__ int slot;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *other = 0;
+    for (int w = next_item(queue, &slot); w < nitems; w = next_item(queue, &slot)) {
         const WorkItem it = items[w];
         const Problem P = probs[it.prob];
         const long long c = (long long)it.tile * WG + threadIdx.x;
@@ -1368,18 +1386,22 @@ hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStre
     } while (0)
 
 hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int grid,
-                                    int maxd, int storage, hipStream_t s) {
+                                    int maxd, int storage, int* queue, int* other, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-#define CDG_L(TT, MD) hipLaunchKernelGGL((k_face_sums_batched<TT, MD>), dim3(grid), dim3(WG), 0, s, probs, items, nitems)
+#define CDG_L(TT, MD)                                                                                       \
+    hipLaunchKernelGGL((k_face_sums_batched<TT, MD>), dim3(grid), dim3(WG), 0, s, probs, items, nitems, queue, \
+                       other)
     CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
 #undef CDG_L
     return hipGetLastError();
 }
 
 hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, int nitems, int grid, int maxd,
-                                 int storage, hipStream_t s) {
+                                 int storage, int* queue, int* other, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-#define CDG_L(TT, MD) hipLaunchKernelGGL((k_update_batched<TT, MD>), dim3(grid), dim3(WG), 0, s, probs, items, nitems)
+#define CDG_L(TT, MD)                                                                                    \
+    hipLaunchKernelGGL((k_update_batched<TT, MD>), dim3(grid), dim3(WG), 0, s, probs, items, nitems, queue, \
+                       other)
     CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
 #undef CDG_L
     return hipGetLastError();

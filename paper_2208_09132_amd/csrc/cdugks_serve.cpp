@@ -40,6 +40,7 @@ struct StorageClass {
     int n_fs = 0, grid_fs = 0;
     WorkItem* items_up = nullptr;  // device
     int n_up = 0, grid_up = 0;
+    int* queue = nullptr;  // device work counters: [0] face sums, [1] update
 };
 
 int device_cus() {
@@ -138,13 +139,15 @@ hipError_t enqueue_batch_step(cdugks_batch* b, int phase) {
     const int np = (int)b->ctxs.size();
     const Problem* probs = b->d_probs[phase];
     for (auto& c : b->classes)
-        if ((e = launch_face_sums_batched(probs, c.items_fs, c.n_fs, c.grid_fs, c.maxd, c.storage, b->stream)) !=
+        if ((e = launch_face_sums_batched(probs, c.items_fs, c.n_fs, c.grid_fs, c.maxd, c.storage, c.queue,
+                                          c.queue + 1, b->stream)) !=
             hipSuccess)
             return e;
     if ((e = launch_face_close_batched(probs, b->d_face_off, np, b->face_total, b->stream)) != hipSuccess) return e;
     if ((e = launch_cell_close_batched(probs, b->d_cell_off, np, b->cell_total, b->stream)) != hipSuccess) return e;
     for (auto& c : b->classes)
-        if ((e = launch_update_batched(probs, c.items_up, c.n_up, c.grid_up, c.maxd, c.storage, b->stream)) !=
+        if ((e = launch_update_batched(probs, c.items_up, c.n_up, c.grid_up, c.maxd, c.storage, c.queue + 1,
+                                       c.queue, b->stream)) !=
             hipSuccess)
             return e;
     return hipSuccess;
@@ -263,12 +266,13 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
     };
     size_t o_p0 = reserve(sizeof(Problem) * count), o_p1 = reserve(sizeof(Problem) * count);
     size_t o_fo = reserve(sizeof(long long) * count), o_co = reserve(sizeof(long long) * count);
-    size_t o_fs[2], o_up[2];
+    size_t o_fs[2], o_up[2], o_q[2];
     for (int s = 0; s < 2; ++s) {
         sort_by_cost(fs[s], cfs[s]);
         sort_by_cost(up[s], cup[s]);
         o_fs[s] = reserve(sizeof(WorkItem) * std::max<size_t>(1, fs[s].size()));
         o_up[s] = reserve(sizeof(WorkItem) * std::max<size_t>(1, up[s].size()));
+        o_q[s] = reserve(2 * sizeof(int));  // zero in the uploaded image
     }
     hipError_t e = hipMalloc(&b->dev, bytes);
     if (e != hipSuccess) {
@@ -310,6 +314,7 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
         sc.items_fs = (WorkItem*)(b->dev + o_fs[s]);
         sc.n_fs = (int)fs[s].size();
         sc.grid_fs = (int)std::min<long long>(sc.n_fs, (long long)cus * bfs * gf);
+        sc.queue = (int*)(b->dev + o_q[s]);
         sc.items_up = (WorkItem*)(b->dev + o_up[s]);
         sc.n_up = (int)up[s].size();
         sc.grid_up = (int)std::min<long long>(sc.n_up, (long long)cus * bup * gf);
