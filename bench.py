@@ -60,7 +60,11 @@ def time_gpu(prob, steps: int, warmup: int, copy_calibration: bool = False):
     import torch
     from paper_2208_09132_amd import cdugks as cd
 
+    torch.cuda.synchronize()
+    t_init0 = time.perf_counter()
     s = cd.Solver(prob, use_torch=True)
+    s.sync()
+    t_init = time.perf_counter() - t_init0
     N, V = s.N, s.V
     s.step(warmup)
     s.sync()
@@ -70,6 +74,9 @@ def time_gpu(prob, steps: int, warmup: int, copy_calibration: bool = False):
     s.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    t_read0 = time.perf_counter()
+    s.moments()  # host copies of rho, u, T
+    t_read = time.perf_counter() - t_read0
     # per-kernel durations from HIP events on the context's stream
     phase_ms = s.profile_phases(max(3, min(steps, 10)))
     if copy_calibration:
@@ -77,7 +84,7 @@ def time_gpu(prob, steps: int, warmup: int, copy_calibration: bool = False):
         # each): a plain copy of known size for calibrating HBM counters
         s.distributions()
     s.close()
-    return N, V, wall, phase_ms
+    return N, V, wall, phase_ms, {"init_s": t_init, "moments_readback_s": t_read}
 
 
 def copy_ceiling(nbytes: int = 1 << 32):
@@ -211,7 +218,7 @@ def main():
     torch.cuda.set_device(0)
 
     name, prob = workload(args.config, "f64")
-    N, V, wall, phase_ms = time_gpu(prob, args.steps, args.warmup, args.copy_calibration)
+    N, V, wall, phase_ms, io = time_gpu(prob, args.steps, args.warmup, args.copy_calibration)
     ups = N * V * args.steps / wall
     ms_step = 1e3 * wall / args.steps
 
@@ -234,11 +241,15 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": name, "cells": list(prob["n"]), "velocities": list(prob["nv"]),
                       "storage": "f64", "gamma": prob["gamma"], "Pr": prob["Pr"], "Kn": prob["Kn"]},
-           "roofline": roofline}
+           "roofline": roofline,
+           # the boundary takes host moments at init and returns host moments:
+           # the same K steps with that traffic counted (never `value`)
+           "host_boundary": dict(io, pcie_inclusive_updates_per_s=N * V * args.steps /
+                                 (wall + io["init_s"] + io["moments_readback_s"]))}
 
     if not args.no_fp32:
         _, p32 = workload(args.config, "f32")
-        N2, V2, wall2, ph2 = time_gpu(p32, args.steps, args.warmup)
+        N2, V2, wall2, ph2, _ = time_gpu(p32, args.steps, args.warmup)
         ups32 = N2 * V2 * args.steps / wall2
         out["fp32_store"] = {"value": ups32, "unit": "updates/s", "ms_per_step": 1e3 * wall2 / args.steps,
                              "speedup_vs_fp64": ups32 / ups,

@@ -76,6 +76,39 @@ def test_batched_sample_matches_oracle():
         s.close()
 
 
+def test_batched_workload_equals_alone_and_matches_oracle():
+    """The benchmark's batched workload (256 uneven 1D/2D problems, FP32
+    storage, one persistent launch per phase): every problem bitwise equal to
+    its solo run after a 2-step graph chunk plus one step; 8 sampled problems
+    (4 of each dimension, the cheapest for the CPU oracle) within 1e-5."""
+    probs = wl.batched(count=256)
+    steps = 3
+    _log(f"batched workload: {len(probs)} problems, solo runs")
+    ref = [alone(p, steps) for p in probs]
+    solvers = [cd.Solver(p) for p in probs]
+    b = cd.Batch(solvers, chunk_steps=2)
+    b.step(steps)
+    b.close()
+    got = [s.moments() for s in solvers]
+    dts = [s.dt for s in solvers]
+    for s in solvers:
+        s.close()
+    for k, (g, r) in enumerate(zip(got, ref)):
+        for a, c in zip(g, r):
+            assert np.array_equal(a, c), f"problem {k} differs"
+    cost = [int(np.prod(p["n"])) * int(np.prod(p["nv"])) for p in probs]
+    sample = []
+    for dim in (1, 2):
+        idx = sorted((k for k, p in enumerate(probs) if p["dim"] == dim), key=lambda k: cost[k])
+        sample += idx[:4]
+    for k in sample:
+        o = make_oracle(probs[k], dt=dts[k])
+        assert o.step(steps) == 0
+        errs = moment_errors(o.moments(), got[k])
+        _log(f"batched workload vs oracle: problem {k} dim={probs[k]['dim']} errs={errs}")
+        assert max(errs) <= 1e-5
+
+
 def test_autotune_keeps_results():
     p = wl.kelvin_helmholtz(n=48, nv=10)
     a = cd.Solver(p)

@@ -145,6 +145,13 @@ def test_kelvin_helmholtz_full_size_one_step_fp64():
     check_parity(p, 1, 1e-12)
 
 
+def test_kelvin_helmholtz_full_size_one_step_fp32():
+    """The FP32-storage leg of the benchmark (same size), one step against the
+    FP64 oracle."""
+    p = wl.kelvin_helmholtz(storage="f32")
+    check_parity(p, 1, 1e-5)
+
+
 def test_kelvin_helmholtz_full_size_conservation_and_stationarity():
     p = wl.kelvin_helmholtz()
     s = cd.Solver(p)
