@@ -24,7 +24,10 @@
  *     in eq. rhoupdate is inconsistent with eqs. implicit and phiupdate);
  *   - the source integral in the energy update is zero when a = 0;
  *   - a velocity with xi_d = 0 takes the mean of both one-sided values;
- *   - ghost cells: periodic wraps, outflow copies the boundary cell.
+ *   - ghost cells: periodic wraps, outflow copies the boundary cell,
+ *     Dirichlet holds the discrete equilibrium of the side's fixed state; a
+ *     ghost outside along several Dirichlet dimensions takes the state of the
+ *     highest of them (ghost layers filled dimension by dimension).
  */
 #include "cdugks_oracle.h"
 
@@ -51,6 +54,8 @@ struct oracle_state {
     double *W;       /* [N][D+2] */
     double t;
     long steps;
+    /* primitives of the Dirichlet states [dim][side] (set when used) */
+    struct prim_s* dprim;
 };
 
 /* ------------------------------------------------------------------ */
@@ -93,6 +98,18 @@ static void ext_coords(const oracle_state* s, long e, long c[3])
     }
 }
 
+/* Dirichlet side (2 d + side) whose state fills the ghost cell c, or -1. */
+static int dirichlet_side(const oracle_state* s, const long c[3])
+{
+    int k = -1;
+    for (int d = 0; d < s->D; ++d) {
+        if (s->p.bc[d] != ORC_BC_DIRICHLET) continue;
+        if (c[d] < 0) k = 2 * d;
+        else if (c[d] >= s->p.n[d]) k = 2 * d + 1;
+    }
+    return k;
+}
+
 /* eq. VanLeer: sigma = (sgn s1 + sgn s2) |s1||s2| / (|s1| + |s2|), and 0
  * when both one-sided derivatives vanish. */
 double oracle_van_leer(double s1, double s2)
@@ -125,7 +142,7 @@ void oracle_velocity_axis(long nv, double vmin, double vmax, int quad,
     }
 }
 
-typedef struct {
+typedef struct prim_s {
     double rho, u[3], T, RT;
     double inv_tau_g, inv_tau_b, inv_tau_bg;
     int bad;
@@ -215,6 +232,19 @@ void oracle_equilibrium_moments(const oracle_state* s, double rho, const double*
 /* life cycle                                                           */
 /* ------------------------------------------------------------------ */
 
+/* Conserved variables of (rho, u, T): rho E = rho u^2/2 + rho c_v T with
+ * c_v = (3+K)R/2 = R/(gamma-1).  u has stride ustride between components. */
+static void conserved_of(const oracle_state* s, double rho, const double* u, long ustride, double T, double* Wc)
+{
+    double u2 = 0.0;
+    Wc[0] = rho;
+    for (int d = 0; d < s->D; ++d) {
+        Wc[1 + d] = rho * u[d * ustride];
+        u2 += u[d * ustride] * u[d * ustride];
+    }
+    Wc[s->D + 1] = rho * (0.5 * u2 + s->p.R * T / (s->p.gamma - 1.0));
+}
+
 oracle_state* oracle_create(const oracle_params* p)
 {
     if (p->dim < 1 || p->dim > 3) return NULL;
@@ -274,13 +304,28 @@ oracle_state* oracle_create(const oracle_params* p)
         }
         s->w[i] = wi;
     }
+
+    /* Dirichlet states: validated, kept as primitives */
+    s->dprim = (prim_t*)calloc(6, sizeof(prim_t));
+    if (!s->dprim) { oracle_destroy(s); return NULL; }
+    for (int d = 0; d < s->D; ++d) {
+        if (p->bc[d] != ORC_BC_DIRICHLET) continue;
+        for (int side = 0; side < 2; ++side) {
+            const double* st = p->dirichlet[d][side];
+            double Wd[5];
+            if (!(st[0] > 0.0) || !(st[4] > 0.0)) { oracle_destroy(s); return NULL; }
+            conserved_of(s, st[0], st + 1, 1, st[4], Wd);
+            s->dprim[2 * d + side] = primitives(s, Wd);
+            if (s->dprim[2 * d + side].bad) { oracle_destroy(s); return NULL; }
+        }
+    }
     return s;
 }
 
 void oracle_destroy(oracle_state* s)
 {
     if (!s) return;
-    free(s->xi); free(s->w); free(s->g); free(s->b); free(s->W);
+    free(s->xi); free(s->w); free(s->g); free(s->b); free(s->W); free(s->dprim);
     free(s);
 }
 
@@ -292,14 +337,7 @@ int oracle_init(oracle_state* s, const double* rho, const double* u, const doubl
     for (long c = 0; c < N; ++c) {
         if (!(rho[c] > 0.0) || !(T[c] > 0.0)) return -1;
         double* Wc = s->W + c * (D + 2);
-        double u2 = 0.0;
-        Wc[0] = rho[c];
-        for (int d = 0; d < D; ++d) {
-            Wc[1 + d] = rho[c] * u[d * N + c];
-            u2 += u[d * N + c] * u[d * N + c];
-        }
-        /* rho E = rho u^2/2 + rho c_v T with c_v = (3+K)R/2 = R/(gamma-1) */
-        Wc[D + 1] = rho[c] * (0.5 * u2 + s->p.R * T[c] / (s->p.gamma - 1.0));
+        conserved_of(s, rho[c], u + c, N, T[c], Wc);
         prim_t q = primitives(s, Wc);
         for (long i = 0; i < V; ++i) {
             const double* xi = s->xi + 3 * i;
@@ -343,6 +381,19 @@ static int one_step(oracle_state* s)
     for (long e = 0; e < NE; ++e) {
         long c[3];
         ext_coords(s, e, c);
+        const int ds = dirichlet_side(s, c);
+        if (ds >= 0) {
+            /* the ghost holds the equilibrium of the fixed state, so its
+             * relaxation and S_b terms vanish and phi_bar_plus = phi_eq */
+            const prim_t* q = &s->dprim[ds];
+            for (long i = 0; i < V; ++i) {
+                const double* xi = s->xi + 3 * i;
+                double geq = g_equilibrium(s, q, xi);
+                qg[e * V + i] = geq;
+                qb[e * V + i] = b_equilibrium(s, q, xi, geq);
+            }
+            continue;
+        }
         long r = real_cell(s, c);
         const prim_t* q = &cp[r];
         for (long i = 0; i < V; ++i) {
@@ -421,7 +472,7 @@ static int one_step(oracle_state* s)
         NF[d] = 1;
         for (int e2 = 0; e2 < 3; ++e2) {
             nf[d][e2] = s->p.n[e2];
-            if (e2 == d && s->p.bc[d] == ORC_BC_OUTFLOW) nf[d][e2] += 1;
+            if (e2 == d && s->p.bc[d] != ORC_BC_PERIODIC) nf[d][e2] += 1;
             NF[d] *= nf[d][e2];
         }
     }

@@ -17,7 +17,11 @@
 extern "C" {
 #endif
 
-enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1 };
+/* Boundary conditions per dimension: periodic wraps, outflow copies the
+ * boundary cell into the ghost layers, Dirichlet fills them with the
+ * equilibrium of a fixed state per side (Sec. 2.1: boundary conditions enter
+ * through the ghost cells). */
+enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_DIRICHLET = 2 };
 enum { ORC_QUAD_TRAPEZOID = 0, ORC_QUAD_BOOLE = 1 };
 enum { ORC_RELAX_MU = 0, ORC_RELAX_TAU = 1 };
 
@@ -26,6 +30,8 @@ typedef struct {
     long n[3];            /* cells per dimension */
     double lo[3], hi[3];  /* domain box */
     int bc[3];            /* boundary condition per dimension (both sides) */
+    double dirichlet[3][2][5]; /* Dirichlet dims: (rho, u_x, u_y, u_z, T) at the
+                                  low [0] and high [1] side */
     long nv[3];           /* discrete velocities per dimension */
     double vmin[3], vmax[3];
     int quad;             /* velocity quadrature rule */

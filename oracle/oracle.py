@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cdugks_oracle.c")
 LIB = os.path.join(HERE, "libcdugks_oracle.so")
 
-BC = {"periodic": 0, "outflow": 1}
+BC = {"periodic": 0, "outflow": 1, "dirichlet": 2}
 QUAD = {"trapezoid": 0, "boole": 1}
 
 
@@ -43,6 +43,7 @@ class _Params(ctypes.Structure):
         ("lo", ctypes.c_double * 3),
         ("hi", ctypes.c_double * 3),
         ("bc", ctypes.c_int * 3),
+        ("dirichlet", ctypes.c_double * 30),
         ("nv", ctypes.c_long * 3),
         ("vmin", ctypes.c_double * 3),
         ("vmax", ctypes.c_double * 3),
@@ -130,9 +131,10 @@ def cfl_dt(cfl: float, dx_min: float, xi_max: float) -> float:
 class Oracle:
     """One CDUGKS problem on the CPU.
 
-    ``prob`` is a dict with keys dim, n, lo, hi, bc (list of 'periodic'/'outflow'),
-    nv, vmin, vmax, quad, gamma, Pr, R, relax ('mu' or 'tau'), mu_ref, T_ref,
-    omega, tau, dt.
+    ``prob`` is a dict with keys dim, n, lo, hi, bc (list of
+    'periodic'/'outflow'/'dirichlet'), nv, vmin, vmax, quad, gamma, Pr, R,
+    relax ('mu' or 'tau'), mu_ref, T_ref, omega, tau, dt, and for Dirichlet
+    dimensions ``dirichlet[d] = [[rho, u_1..u_D, T] low side, [..] high side]``.
     """
 
     def __init__(self, prob: dict):
@@ -146,6 +148,13 @@ class Oracle:
                 p.lo[d] = float(prob["lo"][d])
                 p.hi[d] = float(prob["hi"][d])
                 p.bc[d] = BC[prob["bc"][d]]
+                if prob["bc"][d] == "dirichlet":
+                    for side in range(2):
+                        st = [float(x) for x in prob["dirichlet"][d][side]]
+                        rho, u, T = st[0], st[1:1 + D], st[1 + D]
+                        row = [rho] + u + [0.0] * (3 - D) + [T]
+                        for k in range(5):
+                            p.dirichlet[(d * 2 + side) * 5 + k] = row[k]
                 p.nv[d] = int(prob["nv"][d])
                 p.vmin[d] = float(prob["vmin"][d])
                 p.vmax[d] = float(prob["vmax"][d])
