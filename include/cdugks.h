@@ -45,10 +45,14 @@ enum {
     CDUGKS_ERR_UNKNOWN = -7
 };
 
-/* Boundary conditions per dimension (both sides).  Periodic wraps; outflow
- * copies the boundary cell into the ghost layers (zero gradient).  The paper
- * uses Dirichlet for Sod (Sec. 3.1) and periodic elsewhere (Sec. 3.4, Sec. 4). */
-enum { CDUGKS_BC_PERIODIC = 0, CDUGKS_BC_OUTFLOW = 1 };
+/* Boundary conditions per dimension.  Periodic wraps; outflow copies the
+ * boundary cell into the ghost layers (zero gradient); Dirichlet holds, on
+ * each side, the discrete equilibrium of a fixed state given in
+ * cdugks_space.dirichlet (the paper's Sod runs, Sec. 3.1; boundary conditions
+ * enter the scheme through the ghost cells, Sec. 2.1).  A ghost outside the
+ * domain along several Dirichlet dimensions takes the state of the highest of
+ * them. */
+enum { CDUGKS_BC_PERIODIC = 0, CDUGKS_BC_OUTFLOW = 1, CDUGKS_BC_DIRICHLET = 2 };
 
 /* How the relaxation time is given (Sec. 2, eq. visc and tau_g = mu/p):
  *  KN : Knudsen number; hard-sphere mean free path 16 mu/(5 rho sqrt(2 pi R T))
@@ -73,6 +77,9 @@ typedef struct {
     int64_t n[3];           /* cells per dimension (entries >= dim ignored) */
     double lo[3], hi[3];    /* domain box; uniform Cartesian cells */
     int bc[3];              /* CDUGKS_BC_* per dimension */
+    double dirichlet[3][2][5]; /* DIRICHLET dimensions: (rho, u_x, u_y, u_z, T) on
+                                  the low [0] and high [1] side; rho, T > 0;
+                                  velocity components >= dim are ignored */
 } cdugks_space;
 
 typedef struct {
@@ -111,7 +118,8 @@ int cdugks_required_bytes(const cdugks_space* space, const cdugks_velocity* vel,
  * cdugks_required_bytes figure, 256-byte aligned) may be NULL, in which case
  * the library allocates.  Validation failures return CDUGKS_ERR_INVALID:
  * dim outside 1..3, n < 1, nv < 2, Boole with nv != 4k+1, gamma outside
- * (1, 5/3], Pr <= 0, R <= 0, rho <= 0, T <= 0, a requested dt above the CFL
+ * (1, 5/3], Pr <= 0, R <= 0, rho <= 0, T <= 0 (in a cell or a Dirichlet
+ * state), an unknown boundary condition, a requested dt above the CFL
  * bound, and sizes beyond the kernels' index ranges (faces >= 2^31,
  * velocities >= 2^24, cells x velocities > 2^40; cdugks_required_bytes
  * rejects these too).  Returns after enqueueing the initialisation. */

@@ -22,7 +22,7 @@ LIB_PATH = os.environ.get("CDUGKS_LIBRARY") or os.path.join(HERE, "libcdugks.so"
 
 OK, PENDING = 0, 1
 ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_NONPHYSICAL, ERR_TOO_LARGE, ERR_BUSY, ERR_UNKNOWN = -1, -2, -3, -4, -5, -6, -7
-BC = {"periodic": 0, "outflow": 1}
+BC = {"periodic": 0, "outflow": 1, "dirichlet": 2}
 RELAX = {"kn": 0, "mu": 1, "tau": 2}
 QUAD = {"trapezoid": 0, "boole": 1}
 STORE = {"f64": 0, "f32": 1}
@@ -40,7 +40,8 @@ class CdugksError(RuntimeError):
 
 class cdugks_space(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_double * 3),
-                ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3)]
+                ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3),
+                ("dirichlet", ctypes.c_double * 30)]  # [3][2][5]: (rho, u_x, u_y, u_z, T)
 
 
 class cdugks_velocity(ctypes.Structure):
@@ -132,6 +133,13 @@ def describe(prob: dict):
             sp.lo[d] = float(prob["lo"][d])
             sp.hi[d] = float(prob["hi"][d])
             sp.bc[d] = BC[prob["bc"][d]]
+            if prob["bc"][d] == "dirichlet":
+                # prob["dirichlet"][d] = [[rho, u_1..u_D, T] low side, [...] high side]
+                for side in range(2):
+                    st = [float(x) for x in prob["dirichlet"][d][side]]
+                    row = [st[0]] + st[1:1 + D] + [0.0] * (3 - D) + [st[1 + D]]
+                    for k in range(5):
+                        sp.dirichlet[(d * 2 + side) * 5 + k] = row[k]
             ve.nv[d] = int(prob["nv"][d])
             ve.vmin[d] = float(prob["vmin"][d])
             ve.vmax[d] = float(prob["vmax"][d])

@@ -48,8 +48,21 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
         if (d < D) {
             if (sp->n[d] < 1 || sp->n[d] > (1 << 24)) return fail(CDUGKS_ERR_INVALID, "n[%d] out of range", d);
             if (!(sp->hi[d] > sp->lo[d])) return fail(CDUGKS_ERR_INVALID, "empty domain along %d", d);
-            if (sp->bc[d] != CDUGKS_BC_PERIODIC && sp->bc[d] != CDUGKS_BC_OUTFLOW)
+            if (sp->bc[d] != CDUGKS_BC_PERIODIC && sp->bc[d] != CDUGKS_BC_OUTFLOW &&
+                sp->bc[d] != CDUGKS_BC_DIRICHLET)
                 return fail(CDUGKS_ERR_INVALID, "unsupported boundary condition %d along %d", sp->bc[d], d);
+            if (sp->bc[d] == CDUGKS_BC_DIRICHLET) {
+                for (int side = 0; side < 2; ++side) {
+                    const double* st = sp->dirichlet[d][side];
+                    bool ok = st[0] > 0.0 && st[4] > 0.0 && std::isfinite(st[0]) && std::isfinite(st[4]);
+                    for (int e = 0; e < D; ++e) ok = ok && std::isfinite(st[1 + e]);
+                    if (!ok)
+                        return fail(CDUGKS_ERR_INVALID, "Dirichlet state along %d (side %d) needs rho > 0, T > 0",
+                                    d, side);
+                    for (int k = 0; k < 5; ++k) r.dir[d][side][k] = k >= 1 && k <= 3 && k - 1 >= D ? 0.0 : st[k];
+                }
+                r.any_dirichlet = true;
+            }
             if (ve->nv[d] < 2 || ve->nv[d] > 4096) return fail(CDUGKS_ERR_INVALID, "nv[%d] must be in [2, 4096]", d);
             if (!(ve->vmax[d] > ve->vmin[d])) return fail(CDUGKS_ERR_INVALID, "empty velocity box along %d", d);
             if (ve->quadrature == CDUGKS_QUAD_BOOLE && (ve->nv[d] - 1) % 4 != 0)
@@ -57,7 +70,8 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
                             (long long)ve->nv[d]);
             r.n[d] = (int)sp->n[d];
             r.bc[d] = sp->bc[d];
-            r.ne[d] = r.n[d] + (r.bc[d] == CDUGKS_BC_OUTFLOW ? 1 : 0);
+            // outflow and Dirichlet dimensions carry both boundary faces
+            r.ne[d] = r.n[d] + (r.bc[d] != CDUGKS_BC_PERIODIC ? 1 : 0);
             r.nv[d] = (int)ve->nv[d];
             r.dx[d] = (sp->hi[d] - sp->lo[d]) / r.n[d];
         } else {
@@ -210,6 +224,7 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
         r.off_W[k] = take((size_t)(D + 2) * r.N * 8);
         r.off_P[k] = take((size_t)NPC * r.N * 8);
     }
+    r.off_dir = r.any_dirichlet ? take((size_t)2 * D * r.V * 2 * 8) : 0;
     r.off_q[0] = quarter_stored(D) ? take(NV * es) : 0;
     r.off_q[1] = quarter_stored(D) ? take(NV * es) : 0;
     // face values: 2D blocks of V NE values, each block padded by the stagger
@@ -305,6 +320,37 @@ void velocity_tables(const Resolved& r, std::vector<double>& vel, std::vector<do
     for (int d = 0; d < 3; ++d) axis.insert(axis.end(), wts[d].begin(), wts[d].end());
 }
 
+// Discrete equilibria of the Dirichlet states, [2 d + side][V][g_eq, b_eq]
+// (eqs. geq, beq; the ghost cells hold them, so their quarter-step value is
+// the equilibrium itself).  Sides of non-Dirichlet dimensions stay zero.
+void dirichlet_tables(const Resolved& r, const std::vector<double>& vel, std::vector<double>& out) {
+    const int D = r.D;
+    out.assign((size_t)2 * D * r.V * 2, 0.0);
+    for (int d = 0; d < D; ++d) {
+        if (r.bc[d] != CDUGKS_BC_DIRICHLET) continue;
+        for (int side = 0; side < 2; ++side) {
+            const double* st = r.dir[d][side];
+            const double rho = st[0], RT = r.R * st[4];
+            const double two_pi_rt = 2.0 * M_PI * RT;
+            const double A = rho * (D == 1 ? 1.0 / std::sqrt(two_pi_rt)
+                                           : (D == 2 ? 1.0 / two_pi_rt : 1.0 / (two_pi_rt * std::sqrt(two_pi_rt))));
+            const double inv2RT = 0.5 / RT, cRT2 = 0.5 * r.c_int * RT;
+            double* o = out.data() + (size_t)(2 * d + side) * r.V * 2;
+            for (long long i = 0; i < r.V; ++i) {
+                const double* v = vel.data() + i * NVEL;
+                double c2 = 0.0;
+                for (int e = 0; e < D; ++e) {
+                    const double x = v[VE_XI0 + e] - st[1 + e];
+                    c2 += x * x;
+                }
+                const double geq = A * std::exp(-c2 * inv2RT);
+                o[2 * i] = geq;
+                o[2 * i + 1] = (v[VE_HX2] + cRT2) * geq;
+            }
+        }
+    }
+}
+
 void fill_problem(const Resolved& r, char* base, Problem& P) {
     std::memset(&P, 0, sizeof P);
     P.D = r.D;
@@ -343,6 +389,7 @@ void fill_problem(const Resolved& r, char* base, Problem& P) {
     }
     P.FV = base + r.off_FV;
     P.fv_stride = r.fv_stride;
+    P.dir_eq = r.any_dirichlet ? (const double*)(base + r.off_dir) : nullptr;
     P.FS = (double*)(base + r.off_FS);
     P.FP = (double*)(base + r.off_FP);
     P.G = (double*)(base + r.off_G);
@@ -477,6 +524,8 @@ int cdugks_init(const cdugks_space* space, const cdugks_velocity* vel, const cdu
 
     std::vector<double> veltab, axis;
     velocity_tables(r, veltab, axis);
+    std::vector<double> dirtab;
+    if (r.any_dirichlet) dirichlet_tables(r, veltab, dirtab);
     // moments staged in the scratch region for the init kernel
     std::vector<double> stage((size_t)(r.D + 2) * r.N);
     std::memcpy(stage.data(), rho, sizeof(double) * r.N);
@@ -488,6 +537,8 @@ int cdugks_init(const cdugks_space* space, const cdugks_velocity* vel, const cdu
                             c->stream)) != hipSuccess ||
         (e = hipMemcpyAsync(c->base + r.off_axis, axis.data(), axis.size() * 8, hipMemcpyHostToDevice,
                             c->stream)) != hipSuccess ||
+        (r.any_dirichlet && (e = hipMemcpyAsync(c->base + r.off_dir, dirtab.data(), dirtab.size() * 8,
+                                                 hipMemcpyHostToDevice, c->stream)) != hipSuccess) ||
         (e = hipMemcpyAsync(scratch, stage.data(), stage.size() * 8, hipMemcpyHostToDevice, c->stream)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(c->base + r.off_err, zero, sizeof zero, hipMemcpyHostToDevice, c->stream)) !=

@@ -25,9 +25,11 @@ struct Resolved {
     double dt, gamma, Pr, R, omega, K, c_int, mu_ref, T_ref, tau_inv;
     // byte offsets inside the problem's device block
     size_t off_g[2], off_b[2], off_W[2], off_P[2];
-    size_t off_q[2], off_FV, off_FS, off_FP, off_G, off_vel, off_axis, off_err, off_scratch;
+    size_t off_q[2], off_dir, off_FV, off_FS, off_FP, off_G, off_vel, off_axis, off_err, off_scratch;
     size_t bytes;
     long long fv_stride;  // elements between the (d, field) blocks of the face values
+    double dir[3][2][5];  // Dirichlet states (rho, u_x, u_y, u_z, T) per dimension and side
+    bool any_dirichlet;
 };
 
 // Steps per captured graph of a single context.
@@ -39,6 +41,7 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
             const double* rho, Resolved* out);
 void resident_slots(int D, int storage, long long* R1, long long* R2);
 void velocity_tables(const Resolved& r, std::vector<double>& vel, std::vector<double>& axis);
+void dirichlet_tables(const Resolved& r, const std::vector<double>& vel, std::vector<double>& out);
 void fill_problem(const Resolved& r, char* base, Problem& P);
 void set_pingpong(Problem& P, const Resolved& r, char* base, int cur);
 hipError_t enqueue_step(const Problem& P, hipStream_t s);

@@ -50,7 +50,7 @@ struct Problem {
     int relax;         // 0: mu law, 1: constant tau
     int n[3];          // cells per dimension (1 when unused)
     int ne[3];         // extended (face) grid: n + 1 for outflow dims
-    int bc[3];         // 0 periodic, 1 outflow
+    int bc[3];         // 0 periodic, 1 outflow, 2 Dirichlet
     int nv[3];
     int V;
     int tiles1[3];     // tiles per dimension over the face grid (face-sum kernel)
@@ -73,6 +73,7 @@ struct Problem {
     double* FP;   // face coefficients [D][NFP][NE]
     double* G;    // flux moments [D][D+2][NE]
     int* err;     // sticky non-physical flag
+    const double* dir_eq;  // Dirichlet ghosts: [2 d + side][V][g_eq, b_eq], or null
 };
 
 // One workgroup's assignment in a batched launch.
@@ -95,14 +96,15 @@ hipError_t launch_moments(const Problem& P, const double* W, double* rho, double
                           hipStream_t s);
 hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStream_t s);
 
-// Batched: one launch per phase across problems of one storage class.  The
+// Batched: one launch per phase across problems of one class (storage, and
+// whether they have Dirichlet sides, which selects the face-sum variant).  The
 // tile-kernel launches are persistent (grid = resident slots; workgroups take
 // items from the device counter `queue`, which must be 0 at launch, and reset
 // the counter `other` of the other kernel of the pair); maxd is the largest
 // dimension in the class.  The per-face and per-cell closures take
 // per-problem prefix offsets (in threads).
 hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int grid,
-                                    int maxd, int storage, int* queue, int* other, hipStream_t s);
+                                    int maxd, int storage, bool dirichlet, int* queue, int* other, hipStream_t s);
 hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, int nitems, int grid, int maxd,
                                  int storage, int* queue, int* other, hipStream_t s);
 int batched_blocks_per_cu(int maxd, int storage, bool update);

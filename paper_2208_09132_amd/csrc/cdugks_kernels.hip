@@ -451,7 +451,10 @@ struct GaussWalk {
 // of each tile cell along each d (stored for the update kernel), and the
 // velocity sums of the face (serial per thread, fixed order)
 // ---------------------------------------------------------------------------
-template <int D, typename ST>
+// DIR: the problem has Dirichlet sides; their ghost slots of the q box take
+// the fixed states' equilibria (a separate instantiation keeps the register
+// budget of the others unchanged).
+template <int D, typename ST, bool DIR = false>
 struct FaceSumKernel {
     using G = Geo<D>;
     // stencil arithmetic (quarter-step values in LDS, limiters, face values) in
@@ -536,6 +539,8 @@ struct FaceSumKernel {
         // q-box points of this thread: slot 0 its own cell, then halo points
         // (halo enumerated in box order, interior skipped); source cell after
         // periodic wrap / outflow clamp
+        // lq: box index in the low 20 bits; for a Dirichlet ghost, its side
+        // 2 d + side plus one in the bits above (-1: unused slot)
         long long srcq[NSLOT];
         int lq[NSLOT];
         CellCoef kq[KQ ? NSLOT : 1];
@@ -553,9 +558,17 @@ struct FaceSumKernel {
                 if (lq[k] < 0) continue;
                 int r = lq[k];
                 int rx = r % G::QX, ry = (r / G::QX) % G::QY, rz = r / (G::QX * G::QY);
-                int cx = map_coord(ox + rx - G::OQX, P.n[0], P.bc[0]);
-                int cy = D >= 2 ? map_coord(oy + ry - G::OQY, P.n[1], P.bc[1]) : 0;
-                int cz = D >= 3 ? map_coord(oz + rz - G::OQZ, P.n[2], P.bc[2]) : 0;
+                const int c3[3] = {ox + rx - G::OQX, oy + ry - G::OQY, oz + rz - G::OQZ};
+                if constexpr (DIR) {
+                    int side = 0;
+#pragma unroll
+                    for (int d = 0; d < D; ++d)
+                        if (P.bc[d] == 2 && (c3[d] < 0 || c3[d] >= P.n[d])) side = 2 * d + (c3[d] >= P.n[d]) + 1;
+                    lq[k] = r | (side << 20);
+                }
+                int cx = map_coord(c3[0], P.n[0], P.bc[0]);
+                int cy = D >= 2 ? map_coord(c3[1], P.n[1], P.bc[1]) : 0;
+                int cz = D >= 3 ? map_coord(c3[2], P.n[2], P.bc[2]) : 0;
                 srcq[k] = cx + (long long)P.n[0] * (cy + (long long)P.n[1] * cz);
                 if constexpr (KQ) kq[k] = load_coef(P.P_in, N, srcq[k]);
             }
@@ -669,8 +682,8 @@ struct FaceSumKernel {
             // stage 1: quarter-step fields on the q box
 #pragma unroll
             for (int k = 0; k < NSLOT; ++k) {
-                const int r = lq[k];
-                if (r >= 0) {
+                if (lq[k] >= 0) {
+                    const int r = lq[k] & 0xFFFFF;
                     double g, b;
                     if constexpr (PREFETCH) {
                         g = (double)cur_g[k];
@@ -697,6 +710,13 @@ struct FaceSumKernel {
                     } else {
                         CellCoef kk = load_coef(P.P_in, N, srcq[k]);
                         quarter_step<D>(kk, v, g, b, qg, qb);
+                    }
+                    if constexpr (DIR) {
+                        if (lq[k] >> 20) {  // Dirichlet ghost: the fixed state's equilibrium
+                            const double* de = P.dir_eq + ((long long)((lq[k] >> 20) - 1) * P.V + i) * 2;
+                            qg = de[0];
+                            qb = de[1];
+                        }
                     }
                     sq0[r] = CT(qg);
                     sq1[r] = CT(qb);
@@ -1000,9 +1020,9 @@ struct UpdateKernel {
 template <int D>
 constexpr int face_sum_waves() { return D == 1 ? 4 : (D == 2 ? 3 : 1); }
 
-template <int D, typename ST>
+template <int D, typename ST, bool DIR>
 __global__ __launch_bounds__(WG, face_sum_waves<D>()) void k_face_sums(Problem P) {
-    using K = FaceSumKernel<D, ST>;
+    using K = FaceSumKernel<D, ST, DIR>;
     __shared__ typename K::Smem sm;
     int ntiles = P.tiles1[0] * P.tiles1[1] * P.tiles1[2];
     int q = xcd_remap(blockIdx.x, gridDim.x);
@@ -1026,24 +1046,24 @@ __device__ __forceinline__ int next_item(int* queue, int* slot) {
     return w;
 }
 
-template <typename ST, int MAXD>
+template <typename ST, int MAXD, bool DIR>
 __global__ __launch_bounds__(WG) void k_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems,
                                                           int* queue, int* other) {
     __shared__ union U {
-        typename FaceSumKernel<1, ST>::Smem s1;
-        typename FaceSumKernel<MAXD >= 2 ? 2 : 1, ST>::Smem s2;
-        typename FaceSumKernel<MAXD >= 3 ? 3 : 1, ST>::Smem s3;
+        typename FaceSumKernel<1, ST, DIR>::Smem s1;
+        typename FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR>::Smem s2;
+        typename FaceSumKernel<MAXD >= 3 ? 3 : 1, ST, DIR>::Smem s3;
     } sm;
     __shared__ int slot;
     if (blockIdx.x == 0 && threadIdx.x == 0) *other = 0;
     for (int w = next_item(queue, &slot); w < nitems; w = next_item(queue, &slot)) {
         const WorkItem it = items[w];
         const Problem P = probs[it.prob];
-        if (P.D == 1) FaceSumKernel<1, ST>::run(P, it.tile, it.slice, P.nslices, sm.s1);
+        if (P.D == 1) FaceSumKernel<1, ST, DIR>::run(P, it.tile, it.slice, P.nslices, sm.s1);
         else if (MAXD >= 2 && P.D == 2)
-            FaceSumKernel<MAXD >= 2 ? 2 : 1, ST>::run(P, it.tile, it.slice, P.nslices, sm.s2);
+            FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR>::run(P, it.tile, it.slice, P.nslices, sm.s2);
         else if (MAXD >= 3)
-            FaceSumKernel<MAXD >= 3 ? 3 : 1, ST>::run(P, it.tile, it.slice, P.nslices, sm.s3);
+            FaceSumKernel<MAXD >= 3 ? 3 : 1, ST, DIR>::run(P, it.tile, it.slice, P.nslices, sm.s3);
     }
 }
 
@@ -1314,9 +1334,15 @@ hipError_t launch_init(const Problem& P, const double* rho, const double* u, con
 
 hipError_t launch_face_sums(const Problem& P, hipStream_t s) {
     unsigned nb = (unsigned)(P.tiles1[0] * P.tiles1[1] * P.tiles1[2] * P.nslices);
-#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT>), dim3(nb), dim3(WG), 0, s, P)
-    CDG_DISPATCH(P.storage, P.D, CDG_L);
+    if (P.dir_eq) {
+#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT, true>), dim3(nb), dim3(WG), 0, s, P)
+        CDG_DISPATCH(P.storage, P.D, CDG_L);
 #undef CDG_L
+    } else {
+#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT, false>), dim3(nb), dim3(WG), 0, s, P)
+        CDG_DISPATCH(P.storage, P.D, CDG_L);
+#undef CDG_L
+    }
     return hipGetLastError();
 }
 
@@ -1336,7 +1362,7 @@ int tile_blocks_per_cu(int D, int storage, bool update) {
         CDG_DISPATCH(storage, D, CDG_L);
 #undef CDG_L
     } else {
-#define CDG_L(DD, TT) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums<DD, TT>), WG, 0)
+#define CDG_L(DD, TT) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums<DD, TT, false>), WG, 0)
         CDG_DISPATCH(storage, D, CDG_L);
 #undef CDG_L
     }
@@ -1386,13 +1412,21 @@ hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStre
     } while (0)
 
 hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int grid,
-                                    int maxd, int storage, int* queue, int* other, hipStream_t s) {
+                                    int maxd, int storage, bool dirichlet, int* queue, int* other, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-#define CDG_L(TT, MD)                                                                                       \
-    hipLaunchKernelGGL((k_face_sums_batched<TT, MD>), dim3(grid), dim3(WG), 0, s, probs, items, nitems, queue, \
-                       other)
-    CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
+    if (dirichlet) {
+#define CDG_L(TT, MD)                                                                                   \
+    hipLaunchKernelGGL((k_face_sums_batched<TT, MD, true>), dim3(grid), dim3(WG), 0, s, probs, items, nitems, \
+                       queue, other)
+        CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
 #undef CDG_L
+    } else {
+#define CDG_L(TT, MD)                                                                                    \
+    hipLaunchKernelGGL((k_face_sums_batched<TT, MD, false>), dim3(grid), dim3(WG), 0, s, probs, items, nitems, \
+                       queue, other)
+        CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
+#undef CDG_L
+    }
     return hipGetLastError();
 }
 
@@ -1415,7 +1449,7 @@ int batched_blocks_per_cu(int maxd, int storage, bool update) {
         CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
 #undef CDG_L
     } else {
-#define CDG_L(TT, MD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums_batched<TT, MD>), WG, 0)
+#define CDG_L(TT, MD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums_batched<TT, MD, false>), WG, 0)
         CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
 #undef CDG_L
     }

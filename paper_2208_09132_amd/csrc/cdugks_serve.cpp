@@ -2,7 +2,8 @@
 // the launch-shape autotuner.
 //
 // Batched: all problems of a batch advance together.  Per step there is one
-// persistent launch per storage class for the face sums and for the update,
+// persistent launch per class (storage precision, and whether the problems
+// have Dirichlet sides) for the face sums and for the update,
 // and one launch each for the per-face and per-cell closures over all
 // problems.  Step sequences are captured as HIP graphs of chunk_steps steps.
 // Every kernel computes each (problem, tile, velocity slice) item exactly as
@@ -35,6 +36,7 @@ namespace {
 
 struct StorageClass {
     int storage = 0;
+    bool dirichlet = false;  // members have Dirichlet sides (face-sum variant)
     int maxd = 1;
     WorkItem* items_fs = nullptr;  // device
     int n_fs = 0, grid_fs = 0;
@@ -139,7 +141,7 @@ hipError_t enqueue_batch_step(cdugks_batch* b, int phase) {
     const int np = (int)b->ctxs.size();
     const Problem* probs = b->d_probs[phase];
     for (auto& c : b->classes)
-        if ((e = launch_face_sums_batched(probs, c.items_fs, c.n_fs, c.grid_fs, c.maxd, c.storage, c.queue,
+        if ((e = launch_face_sums_batched(probs, c.items_fs, c.n_fs, c.grid_fs, c.maxd, c.storage, c.dirichlet, c.queue,
                                           c.queue + 1, b->stream)) !=
             hipSuccess)
             return e;
@@ -227,13 +229,16 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
     }
     b->face_total = ft;
     b->cell_total = ct;
-    // work lists per storage class, sorted by estimated cost (largest first)
-    std::vector<std::vector<WorkItem>> fs(2), up(2);
-    std::vector<std::vector<double>> cfs(2), cup(2);
-    int maxd[2] = {0, 0};
+    // work lists per class (index 2 storage + Dirichlet), sorted by estimated
+    // cost (largest first)
+    constexpr int NCLASS = 4;
+    std::vector<std::vector<WorkItem>> fs(NCLASS), up(NCLASS);
+    std::vector<std::vector<double>> cfs(NCLASS), cup(NCLASS);
+    int maxd[NCLASS] = {0, 0, 0, 0};
+    auto class_of = [](const Resolved& r) { return 2 * r.storage + (r.any_dirichlet ? 1 : 0); };
     for (int j = 0; j < count; ++j) {
         const Resolved& r = ctxs[j]->r;
-        const int s = r.storage;
+        const int s = class_of(r);
         maxd[s] = std::max(maxd[s], r.D);
         const int nt = r.tiles1[0] * r.tiles1[1] * r.tiles1[2];
         const double vpt = (double)r.V / r.nslices;
@@ -266,8 +271,8 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
     };
     size_t o_p0 = reserve(sizeof(Problem) * count), o_p1 = reserve(sizeof(Problem) * count);
     size_t o_fo = reserve(sizeof(long long) * count), o_co = reserve(sizeof(long long) * count);
-    size_t o_fs[2], o_up[2], o_q[2];
-    for (int s = 0; s < 2; ++s) {
+    size_t o_fs[NCLASS], o_up[NCLASS], o_q[NCLASS];
+    for (int s = 0; s < NCLASS; ++s) {
         sort_by_cost(fs[s], cfs[s]);
         sort_by_cost(up[s], cup[s]);
         o_fs[s] = reserve(sizeof(WorkItem) * std::max<size_t>(1, fs[s].size()));
@@ -285,7 +290,7 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
     std::memcpy(host.data() + o_p1, probs[1].data(), sizeof(Problem) * count);
     std::memcpy(host.data() + o_fo, face_off.data(), sizeof(long long) * count);
     std::memcpy(host.data() + o_co, cell_off.data(), sizeof(long long) * count);
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < NCLASS; ++s) {
         if (!fs[s].empty()) std::memcpy(host.data() + o_fs[s], fs[s].data(), sizeof(WorkItem) * fs[s].size());
         if (!up[s].empty()) std::memcpy(host.data() + o_up[s], up[s].data(), sizeof(WorkItem) * up[s].size());
     }
@@ -299,18 +304,19 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
     b->d_face_off = (long long*)(b->dev + o_fo);
     b->d_cell_off = (long long*)(b->dev + o_co);
     const int cus = device_cus();
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < NCLASS; ++s) {
         if (fs[s].empty()) continue;
         StorageClass sc;
-        sc.storage = s;
+        sc.storage = s / 2;
+        sc.dirichlet = s % 2 == 1;
         sc.maxd = maxd[s];
         // persistent grids: resident slots (times the tuned factor of the
         // largest class member), never more than the work items
         int gf = 1;
         for (int j = 0; j < count; ++j)
-            if (ctxs[j]->r.storage == s) gf = std::max(gf, tune_lookup(ctxs[j]->r).grid_factor);
-        int bfs = std::max(1, batched_blocks_per_cu(sc.maxd, s, false));
-        int bup = std::max(1, batched_blocks_per_cu(sc.maxd, s, true));
+            if (class_of(ctxs[j]->r) == s) gf = std::max(gf, tune_lookup(ctxs[j]->r).grid_factor);
+        int bfs = std::max(1, batched_blocks_per_cu(sc.maxd, sc.storage, false));
+        int bup = std::max(1, batched_blocks_per_cu(sc.maxd, sc.storage, true));
         sc.items_fs = (WorkItem*)(b->dev + o_fs[s]);
         sc.n_fs = (int)fs[s].size();
         sc.grid_fs = (int)std::min<long long>(sc.n_fs, (long long)cus * bfs * gf);

@@ -7,7 +7,8 @@ from here.
 
 A problem is a plain dict:
 
-    dim, n[D], lo[D], hi[D], bc[D] ('periodic' | 'outflow'),
+    dim, n[D], lo[D], hi[D], bc[D] ('periodic' | 'outflow' | 'dirichlet'),
+    dirichlet[D] (Dirichlet dims: [[rho, u_1..u_D, T] low, [..] high], else None),
     nv[D], vmin[D], vmax[D], quad ('trapezoid' | 'boole'),
     gamma, Pr, R, omega, relax ('kn' | 'mu' | 'tau'), Kn, L_ref, rho_ref, T_ref,
     mu_ref, tau, cfl, dt (None -> from cfl), storage ('f64' | 'f32'),
@@ -70,10 +71,11 @@ def _base(dim, n, lo, hi, bc, nv, vmin, vmax, **kw):
     return p
 
 
-def sod(n: int = 128, nv: int = 64, Kn: float = 1e-3, steps: int = 1024, **kw):
+def sod(n: int = 128, nv: int = 64, Kn: float = 1e-3, steps: int = 1024, boundary: str = "outflow", **kw):
     """1D Sod tube (Sec. 3.1 set-up, benchmark sizes): [0,1], left (1, 0, p=1),
-    right (1/8, 0, p=1/10), outflow, gamma = 5/3, velocities on [-10, 10]."""
-    p = _base(1, [n], [0.0], [1.0], ["outflow"], [nv], [-10.0], [10.0], Kn=Kn,
+    right (1/8, 0, p=1/10), gamma = 5/3, velocities on [-10, 10]; outflow
+    ends, or Dirichlet ends holding the two initial states (the paper's)."""
+    p = _base(1, [n], [0.0], [1.0], [boundary], [nv], [-10.0], [10.0], Kn=Kn,
               steps=steps, **kw)
     (x,) = cell_centres(1, p["n"], p["lo"], p["hi"])
     left = x <= 0.5
@@ -82,6 +84,8 @@ def sod(n: int = 128, nv: int = 64, Kn: float = 1e-3, steps: int = 1024, **kw):
     p["rho"] = rho
     p["u"] = np.zeros((1, n))
     p["T"] = pres / (rho * p["R"])
+    if boundary == "dirichlet":
+        p["dirichlet"] = [[[1.0, 0.0, 1.0 / p["R"]], [0.125, 0.0, 0.1 / (0.125 * p["R"])]]]
     return p
 
 

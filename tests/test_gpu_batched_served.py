@@ -59,6 +59,29 @@ def test_batched_equals_alone_bitwise():
     _log(f"batched: {len(probs)} problems bitwise equal to their solo runs")
 
 
+def test_batched_with_dirichlet_problems_equals_alone_bitwise():
+    """Problems with Dirichlet sides form their own class of the batch (the
+    face-sum variant with boundary states); results stay bitwise equal."""
+    probs = mixed_problems(seed=31, count=4)
+    d1 = wl.sod(n=100, nv=24, boundary="dirichlet")
+    d2 = wl.random_fourier(2, [20, 17], [6, 6], wl.SplitMix64(12), amp=0.2, Kn=1e-2)
+    d2["bc"] = ["dirichlet", "periodic"]
+    d2["dirichlet"] = [[[1.3, 0.2, -0.1, 1.2], [0.9, -0.1, 0.05, 0.8]], None]
+    d2["storage"] = "f32"
+    probs += [d1, d2]
+    steps = 7
+    ref = [alone(p, steps) for p in probs]
+    solvers = [cd.Solver(p) for p in probs]
+    b = cd.Batch(solvers, chunk_steps=3)
+    b.step(steps)
+    b.close()
+    for k, (s, r) in enumerate(zip(solvers, ref)):
+        got = s.moments()
+        for a, c in zip(got, r):
+            assert np.array_equal(a, c), f"problem {k} differs"
+        s.close()
+
+
 def test_batched_sample_matches_oracle():
     probs = mixed_problems(seed=5, count=4)
     solvers = [cd.Solver(p) for p in probs]

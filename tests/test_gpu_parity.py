@@ -55,6 +55,37 @@ def test_sod_full_run_fp64():
     check_parity(p, p["steps"], 1e-12)
 
 
+def test_sod_dirichlet_full_run_fp64():
+    """The paper's Sod set-up with Dirichlet ends, 1024 steps to t = 0.2."""
+    check_parity(wl.sod(boundary="dirichlet"), 1024, 1e-12)
+
+
+def test_dirichlet_sides_differing_from_the_interior():
+    """Dirichlet states unlike the interior drive the boundary cells: a 1D
+    free-streaming reservoir, 2D with a Dirichlet x axis beside periodic and
+    outflow axes (ragged tiles, odd velocity count), FP32, and a 3D Dirichlet
+    z axis."""
+    p = wl.sod(n=300, nv=41, boundary="dirichlet")
+    p["rho"], p["T"], p["u"] = np.ones(300), np.ones(300), np.zeros((1, 300))
+    p["relax"], p["tau"] = "tau", math.inf
+    p["dirichlet"] = [[[2.0, 0.0, 1.0], [0.7, -0.3, 1.4]]]
+    check_parity(p, 150, 1e-12)
+    q = wl.random_fourier(2, [21, 18], [7, 6], wl.SplitMix64(8), amp=0.2, Kn=1e-2)
+    q["bc"] = ["dirichlet", "periodic"]
+    q["dirichlet"] = [[[1.3, 0.2, -0.1, 1.2], [0.9, -0.1, 0.05, 0.8]], None]
+    check_parity(q, 20, 1e-12)
+    r = wl.random_fourier(2, [19, 23], [6, 7], wl.SplitMix64(9), amp=0.2, Kn=1e-1)
+    r["bc"] = ["outflow", "dirichlet"]
+    r["dirichlet"] = [None, [[1.1, 0.0, 0.3, 1.0], [1.2, 0.1, -0.2, 1.3]]]
+    check_parity(r, 15, 1e-12)
+    r32 = dict(r, storage="f32")
+    check_parity(r32, 15, 1e-5)
+    t = wl.random_fourier(3, [9, 10, 11], [5, 5, 5], wl.SplitMix64(10), amp=0.2, Kn=1e-1)
+    t["bc"] = ["periodic", "outflow", "dirichlet"]
+    t["dirichlet"] = [None, None, [[1.2, 0.1, 0.0, 0.2, 1.1], [0.9, 0.0, -0.1, -0.2, 0.9]]]
+    check_parity(t, 4, 1e-12)
+
+
 def test_1d_periodic_ragged_odd_velocities():
     p = wl.random_fourier(1, [300], [33], wl.SplitMix64(41), amp=0.2, Kn=1e-2, Pr=2.0)
     check_parity(p, 30, 1e-12)
