@@ -89,6 +89,22 @@ def sod(n: int = 128, nv: int = 64, Kn: float = 1e-3, steps: int = 1024, boundar
     return p
 
 
+def sod_validation(n: int = 1024, nv: int = 1025, mu_r: float = 1e-6, Pr: float = 2.0 / 3.0,
+                   t_end: float = 0.15, **kw):
+    """The Sec. 3.1 validation set-up: the Sod states on [0,1] with Dirichlet
+    ends, K = 2 internal degrees of freedom (gamma = 7/5), hard-sphere
+    viscosity exponent 1/2 with reference viscosity mu_r at T_r = 1, velocities
+    on [-10, 10] with nv = 4k+1 points and the fourth-order Newton-Cotes
+    (Boole) weights, CFL factor 0.75, run to t_end.  The step count is
+    t_end / dt for the CFL step alpha dx / (2 max|xi|)."""
+    if (nv - 1) % 4:
+        raise ValueError("the Boole rule needs 4k+1 velocities")
+    cfl = kw.pop("cfl", 0.75)
+    steps = int(round(t_end * 2.0 * 10.0 * n / cfl))
+    return sod(n=n, nv=nv, boundary="dirichlet", quad="boole", gamma=1.4, Pr=Pr, relax="mu",
+               mu_ref=mu_r, T_ref=1.0, omega=0.5, cfl=cfl, steps=steps, **kw)
+
+
 def kelvin_helmholtz(n: int = 256, nv: int = 28, Kn: float = 1e-4, steps: int = 2000,
                      seed: int = 2208, storage: str = "f64", **kw):
     """2D sharp-interface Kelvin-Helmholtz layer (Sec. 3.3 family): periodic

@@ -7,6 +7,8 @@ transposed operand) would break.
   conservation (periodic)          -> flux form, W-update sign, source integral
   uniform equilibrium stationary   -> pointwise algebra of every stage
   Sod vs exact Riemann (small Kn)  -> whole step, shock capturing (Sec. 3.1)
+  Sod validation set-up (gamma 7/5) -> K <-> gamma, Dirichlet ends, Boole run
+  Sod Prandtl sweep                -> contact conduction width ~ 1/sqrt(Pr)
   free streaming vs exact          -> reconstruction / transport (tau = inf)
   sound-wave self-convergence      -> second order in space and time
   NS shear decay                   -> viscosity tau_g = mu/p (Sec. 3.4, eq. NSshear)
@@ -304,6 +306,56 @@ def test_sod_small_kn_matches_exact_riemann():
     plateau = (x > xc - 0.08) & (x < xc - 0.03)
     assert np.mean(rho[plateau] * 0.5 * T[plateau]) == pytest.approx(ps, rel=0.03)
     assert np.mean(u[0][plateau]) == pytest.approx(us, rel=0.03)
+
+
+def _sod_validation_profile(n, nv, mu_r, Pr):
+    p = wl.sod_validation(n=n, nv=nv, mu_r=mu_r, Pr=Pr)
+    o = make_oracle(p)
+    assert o.step(p["steps"]) == 0
+    assert o.time == pytest.approx(0.15, rel=1e-12)
+    rho, u, T = o.moments()
+    return (np.arange(n) + 0.5) / n, rho, u[0], T, o.time
+
+
+def test_sod_validation_setup_matches_exact_riemann_gamma_7_5():
+    """Sec. 3.1 validation set-up in the hydrodynamic regime (K = 2 so
+    gamma = 7/5, Dirichlet ends, Boole velocity rule, CFL 0.75, t = 0.15,
+    mu_r = 1e-6) at 256 cells and 257 velocities against the exact Euler
+    solution for gamma = 7/5: a wrong gamma <-> K map or a wrong Dirichlet
+    ghost moves the star state by far more than 0.5%."""
+    x, rho, u, T, t = _sod_validation_profile(256, 257, 1e-6, 2.0 / 3.0)
+    left, right = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    re, ue, pe = rs.riemann_profile(left, right, 1.4, x, 0.5, t)
+    P = rho * 0.5 * T
+    assert np.mean(np.abs(rho - re)) <= 4e-3
+    assert np.mean(np.abs(u - ue)) <= 8e-3
+    assert np.mean(np.abs(P - pe)) <= 3e-3
+    ps, us = rs.riemann_star(left, right, 1.4)
+    xc = 0.5 + us * t
+    plateau = (x > xc - 0.08) & (x < xc - 0.03)
+    assert np.mean(P[plateau]) == pytest.approx(ps, rel=5e-3)
+    assert np.mean(u[plateau]) == pytest.approx(us, rel=5e-3)
+    # the gamma = 5/3 star state is 4% away: the pin separates the two
+    ps53, _ = rs.riemann_star(left, right, 5.0 / 3.0)
+    assert abs(ps53 - ps) / ps > 0.03
+
+
+def test_sod_prandtl_sweep_contact_conduction():
+    """Sec. 3.1 Prandtl sweep (Pr = 2/3, 1, 3/2 at mu_r = 1e-3): the contact
+    keeps the pressure uniform, so its temperature layer is set by heat
+    conduction alone, kappa ~ mu / Pr, and its width grows as sqrt(kappa t).
+    The steepest temperature gradient at the contact therefore scales as
+    sqrt(Pr); the pin holds the ratios to 10%."""
+    grads = []
+    for Pr in (2.0 / 3.0, 1.0, 1.5):
+        x, rho, u, T, t = _sod_validation_profile(256, 129, 1e-3, Pr)
+        _, us = rs.riemann_star((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 1.4)
+        xc = 0.5 + us * t
+        win = (x[:-1] > xc - 0.05) & (x[:-1] < xc + 0.05)
+        grads.append(float(np.max(np.abs(np.diff(T))[win]) * 256))
+    assert grads[0] < grads[1] < grads[2]
+    assert grads[1] / grads[0] == pytest.approx(math.sqrt(1.5), rel=0.1)
+    assert grads[2] / grads[0] == pytest.approx(math.sqrt(2.25), rel=0.1)
 
 
 def test_free_streaming_second_order():
