@@ -284,10 +284,19 @@ oracle_state* oracle_create(const oracle_params* p)
     if (!s->xi || !s->w || !s->g || !s->b || !s->W) { oracle_destroy(s); return NULL; }
 
     /* tensor-product velocity grid: w_i = prod_d omega_d(m_d) */
-    double nodes[3][4096], wts[3][4096];
+    double* nodes[3] = {NULL, NULL, NULL};
+    double* wts[3] = {NULL, NULL, NULL};
+    int axes_ok = 1;
     for (int d = 0; d < s->D; ++d) {
-        if (p->nv[d] > 4096) { oracle_destroy(s); return NULL; }
+        nodes[d] = (double*)malloc((size_t)p->nv[d] * sizeof(double));
+        wts[d] = (double*)malloc((size_t)p->nv[d] * sizeof(double));
+        if (!nodes[d] || !wts[d]) { axes_ok = 0; break; }
         oracle_velocity_axis(p->nv[d], p->vmin[d], p->vmax[d], p->quad, nodes[d], wts[d]);
+    }
+    if (!axes_ok) {
+        for (int d = 0; d < 3; ++d) { free(nodes[d]); free(wts[d]); }
+        oracle_destroy(s);
+        return NULL;
     }
     for (long i = 0; i < s->V; ++i) {
         long m[3];
@@ -304,6 +313,7 @@ oracle_state* oracle_create(const oracle_params* p)
         }
         s->w[i] = wi;
     }
+    for (int d = 0; d < 3; ++d) { free(nodes[d]); free(wts[d]); }
 
     /* Dirichlet states: validated, kept as primitives */
     s->dprim = (prim_t*)calloc(6, sizeof(prim_t));

@@ -63,7 +63,9 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
                 }
                 r.any_dirichlet = true;
             }
-            if (ve->nv[d] < 2 || ve->nv[d] > 4096) return fail(CDUGKS_ERR_INVALID, "nv[%d] must be in [2, 4096]", d);
+            // the product of the counts is bounded below, with the cells
+            if (ve->nv[d] < 2 || ve->nv[d] >= (1LL << 24))
+                return fail(CDUGKS_ERR_INVALID, "nv[%d] must be in [2, 2^24)", d);
             if (!(ve->vmax[d] > ve->vmin[d])) return fail(CDUGKS_ERR_INVALID, "empty velocity box along %d", d);
             if (ve->quadrature == CDUGKS_QUAD_BOOLE && (ve->nv[d] - 1) % 4 != 0)
                 return fail(CDUGKS_ERR_INVALID, "Boole quadrature needs nv = 4k+1 (nv[%d] = %lld)", d,

@@ -105,6 +105,42 @@ def sod_validation(n: int = 1024, nv: int = 1025, mu_r: float = 1e-6, Pr: float 
                mu_ref=mu_r, T_ref=1.0, omega=0.5, cfl=cfl, steps=steps, **kw)
 
 
+def thermoacoustic(n: int = 512, nv: int = 513, Pr: float = 2.0 / 3.0, delta: float = 0.05,
+                   mu_r: float = 1e-3, t_end: float = 4.0, **kw):
+    """Sec. 3 thermoacoustic wave: periodic [0,1] at pressure equilibrium,
+    rho = 1 - delta sin 4 pi x, R T = P0 / rho with P0 = 1, u = 0; K = 2
+    (gamma = 7/5), viscosity exponent 1/2 with mu_r at T_r = 1, velocities on
+    [-10, 10] with nv = 4k+1 points (Boole weights), CFL factor 0.8."""
+    cfl = kw.pop("cfl", 0.8)
+    steps = int(round(t_end * 2.0 * 10.0 * n / cfl))
+    p = _base(1, [n], [0.0], [1.0], ["periodic"], [nv], [-10.0], [10.0], quad="boole", gamma=1.4,
+              Pr=Pr, relax="mu", mu_ref=mu_r, T_ref=1.0, omega=0.5, cfl=cfl, steps=steps, **kw)
+    (x,) = cell_centres(1, p["n"], p["lo"], p["hi"])
+    p["rho"] = 1.0 - delta * np.sin(4.0 * math.pi * x)
+    p["u"] = np.zeros((1, n))
+    p["T"] = 1.0 / (p["rho"] * p["R"])
+    return p
+
+
+def sine_wave(n: int = 128, nv: int = 16385, T0: float = 0.1, mu_r: float = 1e-5, v0: float = 1.0,
+              t_end: float = 0.5, **kw):
+    """Sec. 3 sine-wave perturbation: periodic [0,1], rho = 1, v = v0 sin 2 pi x,
+    T = T0 (the energy per mass is C_v T0 + v^2/2); K = 2 (gamma = 7/5),
+    viscosity exponent 1/2 with mu_r at T_r = 1, velocities on [-6, 6] with
+    nv = 4k+1 points (Boole weights), CFL factor 0.5.  T0 = 1 with t_end = 0.1
+    is the convergence study's variant."""
+    cfl = kw.pop("cfl", 0.5)
+    quad = kw.pop("quad", "boole")
+    steps = int(round(t_end * 2.0 * 6.0 * n / cfl))
+    p = _base(1, [n], [0.0], [1.0], ["periodic"], [nv], [-6.0], [6.0], quad=quad, gamma=1.4,
+              relax="mu", mu_ref=mu_r, T_ref=1.0, omega=0.5, cfl=cfl, steps=steps, **kw)
+    (x,) = cell_centres(1, p["n"], p["lo"], p["hi"])
+    p["rho"] = np.ones(n)
+    p["u"] = (v0 * np.sin(2.0 * math.pi * x))[None, :]
+    p["T"] = np.full(n, T0)
+    return p
+
+
 def kelvin_helmholtz(n: int = 256, nv: int = 28, Kn: float = 1e-4, steps: int = 2000,
                      seed: int = 2208, storage: str = "f64", **kw):
     """2D sharp-interface Kelvin-Helmholtz layer (Sec. 3.3 family): periodic

@@ -6,6 +6,12 @@
   Fluid Dynamics", ch. 4), written here from the mathematics.
 * Navier-Stokes decay of a transverse shear wave (Sec. 3.4, eq. NSshear) and
   isobaric decay of an entropy (temperature) wave by conduction.
+* One Fourier mode of the 1D Navier-Stokes-Fourier equations linearised about
+  a uniform gas at rest (the thermoacoustic wave of Sec. 3), with the
+  transport coefficients of a BGK gas whose translational and internal
+  energy relax together: longitudinal viscosity (3 - gamma) mu, that is
+  4/3 mu plus a bulk viscosity (2/3 - (gamma - 1)) mu, and conductivity
+  c_p mu / Pr.
 """
 import math
 
@@ -100,3 +106,26 @@ def entropy_wave_amplitude(a0, mu, rho, Pr, k, t):
     rho c_p dT/dt = kappa lap T with kappa = c_p mu / Pr, so the rate is
     mu k^2 / (rho Pr)."""
     return a0 * math.exp(-mu * k * k * t / (rho * Pr))
+
+
+def linear_nsf_mode(a0, c0, rho0, T0, R, gamma, mu, Pr, k, t):
+    """rho' = a sin kx, u' = b cos kx, T' = c sin kx under
+
+        d rho'/dt = -rho0 du'/dx
+        rho0 du'/dt = -dp'/dx + mu_L d2u'/dx2,        p' = R (rho0 T' + T0 rho')
+        rho0 c_v dT'/dt = -p0 du'/dx + kappa d2T'/dx2
+
+    with mu_L = (3 - gamma) mu and kappa = c_p mu / Pr, starting from (a0, 0,
+    c0).  Returns (a, b, c) at each time in t (matrix exponential of the 3x3
+    system)."""
+    from scipy.linalg import expm
+    cv = R / (gamma - 1.0)
+    cp = gamma * cv
+    p0 = rho0 * R * T0
+    muL = (3.0 - gamma) * mu
+    kappa = cp * mu / Pr
+    A = np.array([[0.0, rho0 * k, 0.0],
+                  [-R * T0 * k / rho0, -muL * k * k / rho0, -R * k],
+                  [0.0, p0 * k / (rho0 * cv), -kappa * k * k / (rho0 * cv)]])
+    x0 = np.array([a0, 0.0, c0])
+    return np.array([expm(A * tt) @ x0 for tt in np.atleast_1d(t)])

@@ -98,6 +98,18 @@ def test_sizes_beyond_the_index_ranges_are_rejected():
         assert "too large" in str(ei.value)
 
 
+def test_long_velocity_axes_are_accepted():
+    """One axis may carry up to 2^24 - 1 velocities (the Sec. 3 sine-wave
+    problem uses 16385); the total count and the product with the cells are
+    what the index ranges bound."""
+    base = {"dim": 1, "n": [128], "lo": [0.0], "hi": [1.0], "bc": ["periodic"], "vmin": [-6.0],
+            "vmax": [6.0], "relax": "mu", "mu_ref": 1e-3, "quad": "boole"}
+    assert cd.cdugks_required_bytes(dict(base, nv=[16385])) > 2 * 128 * 16385 * 8
+    with pytest.raises(cd.CdugksError) as ei:
+        cd.cdugks_required_bytes(dict(base, nv=[(1 << 24) + 1]))
+    assert ei.value.code == cd.ERR_INVALID
+
+
 def test_null_context_is_rejected():
     lib = cd.load_library()
     assert lib.cdugks_step(None, 1) == cd.ERR_INVALID

@@ -13,6 +13,8 @@ transposed operand) would break.
   sound-wave self-convergence      -> second order in space and time
   NS shear decay                   -> viscosity tau_g = mu/p (Sec. 3.4, eq. NSshear)
   entropy-wave decay vs 1/Pr       -> tau_b = tau_g/Pr (conductivity)
+  thermoacoustic wave vs linear NSF -> sound speed, conduction, energy coupling
+  velocity-grid convergence        -> Newton-Cotes weights in the whole step
   viscous-heating pattern          -> the Z (g - g_eq)/tau_bg source in S_b
   mirror / axis symmetry           -> upwind selection, index and axis mix-ups
   quadrature and limiter           -> Newton-Cotes weights, eq. VanLeer
@@ -426,6 +428,63 @@ def test_shear_wave_decays_at_navier_stokes_rate():
     amp, _, _ = _shear(2.0 / 3.0, mu, tend)
     rate = -math.log(amp / 0.1) / tend
     assert rate == pytest.approx(4 * math.pi ** 2 * mu, rel=0.05)
+
+
+def _fundamental(x, k, rho, u, T):
+    """Coefficients of rho' = a sin kx, u = b cos kx, T' = c sin kx."""
+    S, C = np.sin(k * x), np.cos(k * x)
+    return (2.0 * np.mean((rho - rho.mean()) * S), 2.0 * np.mean(u * C), 2.0 * np.mean((T - T.mean()) * S))
+
+
+@pytest.mark.parametrize("Pr", [2.0 / 3.0, 1.0, 1.5])
+def test_thermoacoustic_wave_follows_linear_navier_stokes_fourier(Pr):
+    """Sec. 3 thermoacoustic wave (rho = 1 - 0.05 sin 4 pi x at uniform
+    pressure, K = 2, mu_r = 1e-3, Boole, CFL 0.8) at 128 cells x 129
+    velocities to t = 1, against the Fourier mode of the linearised equations
+    with conductivity c_p mu / Pr: heat flows into the dense, cold layers,
+    which expand and drive a sound wave.  Density and temperature amplitudes
+    within 1% of their start values, the velocity within 5% of the largest
+    velocity amplitude of the sweep.  A wrong sound speed (gamma), conduction
+    (Pr) or energy coupling moves them by several times that."""
+    n = 128
+    p = wl.thermoacoustic(n=n, nv=129, Pr=Pr, t_end=1.0)
+    o = make_oracle(p)
+    x = (np.arange(n) + 0.5) / n
+    k = 4.0 * math.pi
+    a0, _, c0 = _fundamental(x, k, *[f if i != 1 else f[0] for i, f in enumerate(o.moments())])
+    times, got = [], []
+    for _ in range(4):
+        assert o.step(p["steps"] // 4) == 0
+        rho, u, T = o.moments()
+        times.append(o.time)
+        got.append(_fundamental(x, k, rho, u[0], T))
+    T0 = 1.0 / p["R"]
+    mu = p["mu_ref"] * math.sqrt(T0 / p["T_ref"])
+    want = rs.linear_nsf_mode(a0, c0, 1.0, T0, p["R"], p["gamma"], mu, Pr, k, times)
+    got = np.array(got)
+    assert np.max(np.abs(got[:, 0] - want[:, 0])) <= 0.01 * abs(a0)
+    assert np.max(np.abs(got[:, 1] - want[:, 1])) <= 1.2e-4
+    assert np.max(np.abs(got[:, 2] - want[:, 2])) <= 0.01 * abs(c0)
+    assert np.max(np.abs(want[:, 1])) > 5e-4     # the sound wave is there
+
+
+def test_velocity_grid_convergence_at_least_fourth_order():
+    """Sec. 4 convergence study: the sine-wave collapse with T = 1 at t = 0.1
+    (mu_r = 1e-5, K = 2, Boole on [-6, 6]) at a fixed 256-cell grid; the L1
+    density error against a 257-velocity run falls at least as N_v^-4 from
+    17 to 65 velocities (the paper reports fourth order).  Beyond that the
+    error reaches a floor set by the spatial grid (the upwind switch at
+    xi = 0 leaves a jump of O(dx^2) in the face values)."""
+    res = {}
+    for nv in (17, 33, 65, 257):
+        p = wl.sine_wave(n=256, nv=nv, T0=1.0, t_end=0.1)
+        o = make_oracle(p)
+        assert o.step(p["steps"]) == 0
+        res[nv] = o.moments()[0]
+    err = {nv: float(np.mean(np.abs(res[nv] - res[257]))) for nv in (17, 33, 65)}
+    assert err[17] / err[33] >= 16.0 * 0.9
+    assert err[33] / err[65] >= 16.0
+    assert err[65] < 5e-5
 
 
 def test_entropy_wave_conduction_scales_with_inverse_prandtl():
