@@ -12,6 +12,7 @@ transposed operand) would break.
   free streaming vs exact          -> reconstruction / transport (tau = inf)
   sound-wave self-convergence      -> second order in space and time
   NS shear decay                   -> viscosity tau_g = mu/p (Sec. 3.4, eq. NSshear)
+  shear wave at Kn = 10            -> free-streaming limit of the same wave (closed form)
   entropy-wave decay vs 1/Pr       -> tau_b = tau_g/Pr (conductivity)
   thermoacoustic wave vs linear NSF -> sound speed, conduction, energy coupling
   velocity-grid convergence        -> Newton-Cotes weights in the whole step
@@ -428,6 +429,33 @@ def test_shear_wave_decays_at_navier_stokes_rate():
     amp, _, _ = _shear(2.0 / 3.0, mu, tend)
     rate = -math.log(amp / 0.1) / tend
     assert rate == pytest.approx(4 * math.pi ** 2 * mu, rel=0.05)
+
+
+def test_shear_wave_at_kn_10_follows_free_streaming():
+    """The 3-D shear workload's wave at Kn = 10 (its y-dependence only: a
+    single cell along x, 16 x 16 velocities on [-6, 6]^2, rho = T = 1): the
+    relaxation time (about 11) is far longer than the run, so u_x(y, t)
+    follows free streaming, 0.1 sin(2 pi y) times the discrete
+    sum_j w_j cos(2 pi xi_j t) M(xi_j) / sum_j w_j M(xi_j) over the y nodes
+    (the discrete form of exp(-2 pi^2 R T t^2)); the Navier-Stokes rate with
+    this viscosity would have removed the wave entirely."""
+    ny = 32
+    for tend in (0.2, 0.3):
+        prob = wl._base(2, [1, ny], [0.0, 0.0], [1.0 / ny, 1.0], ["periodic"] * 2, [16, 16], [-6.0, -6.0],
+                        [6.0, 6.0], Kn=10.0, L_ref=1.0)
+        y = (np.arange(ny) + 0.5) / ny
+        prob["rho"] = np.ones(ny)
+        prob["T"] = np.ones(ny)
+        prob["u"] = np.stack([0.1 * np.sin(2 * np.pi * y), np.zeros(ny)])
+        nst = int(math.ceil(tend / oracle_dt(prob)))
+        o = make_oracle(prob, dt=tend / nst)
+        assert o.step(nst) == 0
+        _, u, _ = o.moments()
+        amp = 2.0 * float(np.mean(u[0] * np.sin(2 * np.pi * y))) / 0.1
+        xi, w = orc.velocity_axis(16, -6.0, 6.0)
+        M = np.exp(-xi ** 2)  # 2 R T = 1
+        closed = float(np.sum(w * M * np.cos(2 * np.pi * xi * tend)) / np.sum(w * M))
+        assert abs(amp - closed) <= 0.02 * (1.0 - closed), (tend, amp, closed)
 
 
 def _fundamental(x, k, rho, u, T):
