@@ -66,6 +66,7 @@ def time_gpu(prob, steps: int, warmup: int, copy_calibration: bool = False):
     s.sync()
     t_init = time.perf_counter() - t_init0
     N, V = s.N, s.V
+    bf16_rows = s.storage_info()[0]
     s.step(warmup)
     s.sync()
     torch.cuda.synchronize()
@@ -84,7 +85,7 @@ def time_gpu(prob, steps: int, warmup: int, copy_calibration: bool = False):
         # each): a plain copy of known size for calibrating HBM counters
         s.distributions()
     s.close()
-    return N, V, wall, phase_ms, {"init_s": t_init, "moments_readback_s": t_read}
+    return N, V, wall, phase_ms, {"init_s": t_init, "moments_readback_s": t_read, "bf16_rows": bf16_rows}
 
 
 def copy_ceiling(nbytes: int = 1 << 32):
@@ -132,6 +133,31 @@ def batched_run(count: int, chunk: int, warm_chunks: int = 1, timed_chunks: int 
     return {"value": updates * steps / wall, "unit": "updates/s", "problems": count, "steps": steps,
             "updates_per_step": updates, "ms_per_step": 1e3 * wall / steps, "storage": "f32",
             "dims": {"1d": sum(p["dim"] == 1 for p in probs), "2d": sum(p["dim"] == 2 for p in probs)}}
+
+
+def sequential_run(count: int, storage: str, steps: int = 50):
+    """The same uneven problems as the batched leg, each advanced on its own
+    with the plain single-problem step (one problem after another, the GPU
+    synchronised in between): the per-problem execution that batching
+    replaces."""
+    from paper_2208_09132_amd import cdugks as cd
+    from paper_2208_09132_amd import workloads as wl
+
+    probs = wl.batched(count=count)
+    total, updates = 0.0, 0
+    for p in probs:
+        q = dict(p)
+        q["storage"] = storage
+        s = cd.Solver(q)
+        s.step(steps)  # warm-up (captures the step graph)
+        s.sync()
+        t0 = time.perf_counter()
+        s.step(steps)
+        s.sync()
+        total += time.perf_counter() - t0
+        updates += s.N * s.V * steps
+        s.close()
+    return {"value": updates / total, "unit": "updates/s", "problems": count, "steps": steps, "storage": storage}
 
 
 def served_run(nreq: int, budget_gb: float = 200.0, max_active: int = 64, chunk: int = 100):
@@ -206,6 +232,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--batched-problems", type=int, default=256)
     ap.add_argument("--served-requests", type=int, default=16)
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="skip running the batched leg's problems one by one with the plain step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run the library's FP64 distribution copy (for counter calibration)")
     args = ap.parse_args()
@@ -255,9 +283,23 @@ def main():
                              "speedup_vs_fp64": ups32 / ups,
                              "phase_ms": {k: float(v) for k, v in zip(PHASES, ph2)},
                              "step_algorithmic_frac": ALGO_BYTES["f32"] * ups32 / 1e9 / HBM_PEAK_GBS}
+        # FP32 with the far velocity tails in BF16 (rows fixed at set-up)
+        _, pt = workload(args.config, "f32_bf16tail")
+        N3, V3, wall3, ph3, io3 = time_gpu(pt, args.steps, args.warmup)
+        ups3 = N3 * V3 * args.steps / wall3
+        out["fp32_bf16tail_store"] = {"value": ups3, "unit": "updates/s", "ms_per_step": 1e3 * wall3 / args.steps,
+                                      "speedup_vs_fp64": ups3 / ups, "speedup_vs_fp32": ups3 / ups32,
+                                      "bf16_rows": io3["bf16_rows"], "rows": V3,
+                                      "phase_ms": {k: float(v) for k, v in zip(PHASES, ph3)}}
     if args.batched_problems > 0:
         out["batched"] = batched_run(args.batched_problems, chunk=100)
         out["batched"]["speedup_vs_fp64_plain"] = out["batched"]["value"] / ups
+        if not args.no_sequential:
+            # the same problems one after another with the plain step
+            for st in ("f64", "f32"):
+                seq = sequential_run(args.batched_problems, st)
+                out["batched"][f"same_problems_one_by_one_{st}"] = seq
+                out["batched"][f"speedup_vs_same_problems_one_by_one_{st}"] = out["batched"]["value"] / seq["value"]
     if args.served_requests > 0:
         out["served"] = served_run(args.served_requests)
     out["copy_ceiling_GBps"] = copy_ceiling()

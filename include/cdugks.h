@@ -69,8 +69,15 @@ enum { CDUGKS_QUAD_TRAPEZOID = 0, CDUGKS_QUAD_BOOLE = 1 };
 
 /* Storage precision of g and b in device memory.  The conserved variables,
  * equilibria, velocity sums and relaxation coefficients are FP64 in every
- * mode; F32 only rounds the stored distributions. */
-enum { CDUGKS_STORE_F64 = 0, CDUGKS_STORE_F32 = 1 };
+ * mode; F32 only rounds the stored distributions (and the face values and
+ * stencil arithmetic derived from them).  F32_BF16TAIL is F32 except that
+ * the velocity rows of the far tails hold BF16 (round to nearest even from
+ * the FP32 value): rows whose node lies more than 4 thermal speeds
+ * sqrt(R T_max) from the box of initial bulk velocities (T_max the largest
+ * initial temperature), so every initial Maxwellian is below exp(-8) of its
+ * peak there.  The set is fixed at cdugks_init; cdugks_required_bytes
+ * reserves FP32 rows for it. */
+enum { CDUGKS_STORE_F64 = 0, CDUGKS_STORE_F32 = 1, CDUGKS_STORE_F32_BF16TAIL = 2 };
 
 typedef struct {
     int dim;                /* D = 1, 2 or 3 */
@@ -147,6 +154,11 @@ int cdugks_conserved(cdugks_ctx* ctx, double* W);
 /* Distributions g[V][N], b[V][N] (velocity-major, cells fastest, FP64) copied
  * to host, V = nv[0]*nv[1]*nv[2] with the velocity index x fastest. */
 int cdugks_distributions(cdugks_ctx* ctx, double* g, double* b);
+
+/* Storage of the context's distributions: the number of velocity rows held
+ * in BF16 (0 unless CDUGKS_STORE_F32_BF16TAIL) and the bytes of one state
+ * array (g or b) as laid out.  Either pointer may be NULL. */
+int cdugks_storage_info(cdugks_ctx* ctx, int64_t* bf16_rows, size_t* state_array_bytes);
 
 /* Time step, simulated time and number of completed steps. */
 int cdugks_info(cdugks_ctx* ctx, double* dt, double* t, int64_t* steps);

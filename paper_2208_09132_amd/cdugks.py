@@ -25,7 +25,7 @@ ERR_INVALID, ERR_NOMEM, ERR_DEVICE, ERR_NONPHYSICAL, ERR_TOO_LARGE, ERR_BUSY, ER
 BC = {"periodic": 0, "outflow": 1, "dirichlet": 2}
 RELAX = {"kn": 0, "mu": 1, "tau": 2}
 QUAD = {"trapezoid": 0, "boole": 1}
-STORE = {"f64": 0, "f32": 1}
+STORE = {"f64": 0, "f32": 1, "f32_bf16tail": 2}
 
 ERROR_NAMES = {ERR_INVALID: "ERR_INVALID", ERR_NOMEM: "ERR_NOMEM", ERR_DEVICE: "ERR_DEVICE",
                ERR_NONPHYSICAL: "ERR_NONPHYSICAL", ERR_TOO_LARGE: "ERR_TOO_LARGE", ERR_BUSY: "ERR_BUSY",
@@ -83,6 +83,7 @@ def load_library():
         "cdugks_conserved": (ctypes.c_int, [vp, _DP]),
         "cdugks_distributions": (ctypes.c_int, [vp, _DP, _DP]),
         "cdugks_info": (ctypes.c_int, [vp, _DP, _DP, ctypes.POINTER(i64)]),
+        "cdugks_storage_info": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(sz)]),
         "cdugks_profile_phases": (ctypes.c_int, [vp, i64, _DP]),
         "cdugks_destroy": (None, [vp]),
         "cdugks_batch_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]),
@@ -281,6 +282,12 @@ class Solver:
         n = ctypes.c_int64()
         check(load_library().cdugks_info(self.ctx, ctypes.byref(dt), ctypes.byref(t), ctypes.byref(n)))
         return dt.value, t.value, n.value
+
+    def storage_info(self):
+        """(velocity rows held in BF16, bytes of one state array)."""
+        n, nb = ctypes.c_int64(), ctypes.c_size_t()
+        check(load_library().cdugks_storage_info(self.ctx, ctypes.byref(n), ctypes.byref(nb)))
+        return n.value, nb.value
 
     def profile_phases(self, nsteps: int):
         """Mean per-step kernel durations (ms) from HIP events on the context's

@@ -96,7 +96,8 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
         return fail(CDUGKS_ERR_INVALID, "gamma must lie in (1, 5/3] (got %g)", pa->gamma);
     if (!(pa->Pr > 0.0)) return fail(CDUGKS_ERR_INVALID, "Pr must be > 0");
     if (!(pa->R > 0.0)) return fail(CDUGKS_ERR_INVALID, "R must be > 0");
-    if (pa->storage != CDUGKS_STORE_F64 && pa->storage != CDUGKS_STORE_F32)
+    if (pa->storage != CDUGKS_STORE_F64 && pa->storage != CDUGKS_STORE_F32 &&
+        pa->storage != CDUGKS_STORE_F32_BF16TAIL)
         return fail(CDUGKS_ERR_INVALID, "unknown storage mode %d", pa->storage);
     r.storage = pa->storage;
     r.gamma = pa->gamma;
@@ -208,6 +209,11 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
     // byte plan
     const size_t es = r.storage == CDUGKS_STORE_F64 ? 8 : 4;
     const size_t NV = (size_t)r.N * r.V;
+    // a state array (g, b, quarter-step field): V rows of N values; the
+    // BF16-tail form starts every row on a 256-byte boundary and reserves an
+    // FP32 row for each (which rows hold BF16 is decided at init)
+    const size_t state_bytes =
+        r.storage == CDUGKS_STORE_F32_BF16TAIL ? (size_t)r.V * align_up((size_t)r.N * 4) : NV * es;
     // Consecutive regions are staggered by 4.25 KB each: arrays read at the
     // same element index (g, b, the quarter-step fields, the face values)
     // would otherwise sit at offsets that are multiples of a large power of
@@ -221,14 +227,15 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
         return o;
     };
     for (int k = 0; k < 2; ++k) {
-        r.off_g[k] = take(NV * es);
-        r.off_b[k] = take(NV * es);
+        r.off_g[k] = take(state_bytes);
+        r.off_b[k] = take(state_bytes);
         r.off_W[k] = take((size_t)(D + 2) * r.N * 8);
         r.off_P[k] = take((size_t)NPC * r.N * 8);
     }
     r.off_dir = r.any_dirichlet ? take((size_t)2 * D * r.V * 2 * 8) : 0;
-    r.off_q[0] = quarter_stored(D) ? take(NV * es) : 0;
-    r.off_q[1] = quarter_stored(D) ? take(NV * es) : 0;
+    r.off_q[0] = quarter_stored(D) ? take(state_bytes) : 0;
+    r.off_q[1] = quarter_stored(D) ? take(state_bytes) : 0;
+    r.off_rows = r.storage == CDUGKS_STORE_F32_BF16TAIL ? take((size_t)r.V * 8) : 0;
     // face values: 2D blocks of V NE values, each block padded by the stagger
     r.fv_stride = (long long)r.V * r.NE + (long long)(STAGGER / es);
     r.off_FV = take((size_t)D * 2 * (size_t)r.fv_stride * es);
@@ -248,8 +255,8 @@ void resident_slots(int D, int storage, long long* R1, long long* R2) {
     static std::mutex mu;
     std::lock_guard<std::mutex> lock(mu);
     static int cus = -1;
-    static int cache[3][2][2];
-    static bool have[3][2][2];
+    static int cache[3][3][2];
+    static bool have[3][3][2];
     if (cus < 0) {
         int dev = 0, n = 0;
         hipDeviceProp_t prop;
@@ -396,6 +403,45 @@ void fill_problem(const Resolved& r, char* base, Problem& P) {
     P.FP = (double*)(base + r.off_FP);
     P.G = (double*)(base + r.off_G);
     P.err = (int*)(base + r.off_err);
+    P.rows = r.storage == CDUGKS_STORE_F32_BF16TAIL ? (const long long*)(base + r.off_rows) : nullptr;
+}
+
+// Rows of the BF16-tail form: velocity i is a tail row when, for every
+// initial cell state, |xi_i - u| exceeds TAIL_SIGMAS thermal speeds
+// sqrt(R T), i.e. its equilibrium is below exp(-TAIL_SIGMAS^2 / 2) of the
+// peak: the distance from xi_i to the box spanned by the initial velocities
+// is compared with TAIL_SIGMAS sqrt(R T_max).  Row words: byte offset of the
+// row in a state array, bit 0 set for a BF16 row; rows start on 256-byte
+// boundaries.
+long long tail_rows(const Resolved& r, const std::vector<double>& vel, const double* u, const double* T,
+                    std::vector<long long>& rows) {
+    constexpr double TAIL_SIGMAS = 4.0;
+    const int D = r.D;
+    double umin[3] = {0, 0, 0}, umax[3] = {0, 0, 0}, Tmax = 0.0;
+    for (int d = 0; d < D; ++d) {
+        umin[d] = umax[d] = u[(size_t)d * r.N];
+        for (long long c = 0; c < r.N; ++c) {
+            umin[d] = std::min(umin[d], u[(size_t)d * r.N + c]);
+            umax[d] = std::max(umax[d], u[(size_t)d * r.N + c]);
+        }
+    }
+    for (long long c = 0; c < r.N; ++c) Tmax = std::max(Tmax, T[c]);
+    const double lim2 = TAIL_SIGMAS * TAIL_SIGMAS * r.R * Tmax;
+    rows.assign((size_t)r.V, 0);
+    long long off = 0, ntail = 0;
+    for (long long i = 0; i < r.V; ++i) {
+        double d2 = 0.0;
+        for (int d = 0; d < D; ++d) {
+            const double x = vel[(size_t)i * NVEL + VE_XI0 + d];
+            const double g = x < umin[d] ? umin[d] - x : (x > umax[d] ? x - umax[d] : 0.0);
+            d2 += g * g;
+        }
+        const bool tail = d2 > lim2;
+        rows[i] = off | (tail ? 1 : 0);
+        off += (long long)align_up((size_t)r.N * (tail ? 2 : 4));
+        ntail += tail;
+    }
+    return ntail;
 }
 
 void set_pingpong(Problem& P, const Resolved& r, char* base, int cur) {
@@ -528,6 +574,8 @@ int cdugks_init(const cdugks_space* space, const cdugks_velocity* vel, const cdu
     velocity_tables(r, veltab, axis);
     std::vector<double> dirtab;
     if (r.any_dirichlet) dirichlet_tables(r, veltab, dirtab);
+    std::vector<long long> rowtab;
+    if (r.storage == CDUGKS_STORE_F32_BF16TAIL) c->bf16_rows = tail_rows(r, veltab, u, T, rowtab);
     // moments staged in the scratch region for the init kernel
     std::vector<double> stage((size_t)(r.D + 2) * r.N);
     std::memcpy(stage.data(), rho, sizeof(double) * r.N);
@@ -540,6 +588,8 @@ int cdugks_init(const cdugks_space* space, const cdugks_velocity* vel, const cdu
         (e = hipMemcpyAsync(c->base + r.off_axis, axis.data(), axis.size() * 8, hipMemcpyHostToDevice,
                             c->stream)) != hipSuccess ||
         (r.any_dirichlet && (e = hipMemcpyAsync(c->base + r.off_dir, dirtab.data(), dirtab.size() * 8,
+                                                 hipMemcpyHostToDevice, c->stream)) != hipSuccess) ||
+        (!rowtab.empty() && (e = hipMemcpyAsync(c->base + r.off_rows, rowtab.data(), rowtab.size() * 8,
                                                  hipMemcpyHostToDevice, c->stream)) != hipSuccess) ||
         (e = hipMemcpyAsync(scratch, stage.data(), stage.size() * 8, hipMemcpyHostToDevice, c->stream)) !=
             hipSuccess ||
@@ -571,6 +621,20 @@ int cdugks_init(const cdugks_space* space, const cdugks_velocity* vel, const cdu
         return fail(CDUGKS_ERR_NONPHYSICAL, "non-physical initial state");
     }
     *out = c;
+    return CDUGKS_OK;
+}
+
+int cdugks_storage_info(cdugks_ctx* c, int64_t* bf16_rows, size_t* state_array_bytes) {
+    if (!c) return fail(CDUGKS_ERR_INVALID, "null context");
+    if (bf16_rows) *bf16_rows = c->bf16_rows;
+    if (state_array_bytes) {
+        const Resolved& r = c->r;
+        if (r.storage == CDUGKS_STORE_F32_BF16TAIL)
+            *state_array_bytes = (size_t)(r.V - c->bf16_rows) * align_up((size_t)r.N * 4) +
+                                 (size_t)c->bf16_rows * align_up((size_t)r.N * 2);
+        else
+            *state_array_bytes = (size_t)r.N * r.V * (r.storage == CDUGKS_STORE_F64 ? 8 : 4);
+    }
     return CDUGKS_OK;
 }
 

@@ -26,6 +26,7 @@ struct Resolved {
     // byte offsets inside the problem's device block
     size_t off_g[2], off_b[2], off_W[2], off_P[2];
     size_t off_q[2], off_dir, off_FV, off_FS, off_FP, off_G, off_vel, off_axis, off_err, off_scratch;
+    size_t off_rows;      // BF16-tail form: row words [V]
     size_t bytes;
     long long fv_stride;  // elements between the (d, field) blocks of the face values
     double dir[3][2][5];  // Dirichlet states (rho, u_x, u_y, u_z, T) per dimension and side
@@ -43,6 +44,8 @@ void resident_slots(int D, int storage, long long* R1, long long* R2);
 void velocity_tables(const Resolved& r, std::vector<double>& vel, std::vector<double>& axis);
 void dirichlet_tables(const Resolved& r, const std::vector<double>& vel, std::vector<double>& out);
 void fill_problem(const Resolved& r, char* base, Problem& P);
+long long tail_rows(const Resolved& r, const std::vector<double>& vel, const double* u, const double* T,
+                    std::vector<long long>& rows);
 void set_pingpong(Problem& P, const Resolved& r, char* base, int cur);
 hipError_t enqueue_step(const Problem& P, hipStream_t s);
 int tuned_update_slices(const Resolved& r);
@@ -60,5 +63,6 @@ struct cdugks_ctx {
     int64_t steps = 0;
     int sticky = 0;
     bool in_batch = false;
+    long long bf16_rows = 0;  // BF16-tail form: velocity rows held in BF16
     hipGraphExec_t graph[2] = {nullptr, nullptr};
 };

@@ -44,7 +44,7 @@ constexpr bool quarter_stored(int D) { return D == 3; }
 // Device-side description of one problem.  Pointers are device addresses.
 struct Problem {
     int D;
-    int storage;       // 0 = f64, 1 = f32
+    int storage;       // 0 = f64, 1 = f32, 2 = f32 with BF16 tail rows
     int nslices;       // velocity slices of the face-sum kernel (fixes the summation order)
     int nslices_upd;   // velocity slices of the update kernel (throughput only)
     int relax;         // 0: mu law, 1: constant tau
@@ -74,6 +74,10 @@ struct Problem {
     double* G;    // flux moments [D][D+2][NE]
     int* err;     // sticky non-physical flag
     const double* dir_eq;  // Dirichlet ghosts: [2 d + side][V][g_eq, b_eq], or null
+    // storage 2 (FP32 with BF16 tail rows): byte offset of each velocity row
+    // inside the state arrays g, b and the quarter-step fields, bit 0 set for
+    // a BF16 row; null otherwise
+    const long long* rows;
 };
 
 // One workgroup's assignment in a batched launch.

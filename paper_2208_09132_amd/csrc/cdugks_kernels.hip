@@ -32,6 +32,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace cdg {
 
 constexpr int WG = 256;
@@ -68,14 +70,13 @@ __device__ __forceinline__ double half_van_leer(double a, double b) {
     return p > 0.0 ? v : 0.0;
 }
 
-// FP32 form for the FP32-storage stencil: the hardware reciprocal plus one
-// Newton step.
+// FP32 form for the FP32-storage stencil: the hardware reciprocal alone
+// (within 1 ulp), so the limited slope is within about 2 ulp of the rounded
+// quotient, below the rounding of the FP32 values it is built from and
+// stored as.
 __device__ __forceinline__ float half_van_leer(float a, float b) {
     float p = a * b;
-    float s = a + b;
-    float r = __builtin_amdgcn_rcpf(s);
-    r = fmaf(r, fmaf(-s, r, 1.0f), r);
-    float v = p * r;
+    float v = p * __builtin_amdgcn_rcpf(a + b);
     return p > 0.0f ? v : 0.0f;
 }
 
@@ -97,6 +98,166 @@ __device__ __forceinline__ void st_stream(void* base, long long idx, double v) {
 }
 
 __device__ __forceinline__ void raise_error(int* err) { *err = 1; }
+
+// ---------------------------------------------------------------------------
+// storage forms of the distributions g, b (and of the 3-D quarter-step fields)
+// ---------------------------------------------------------------------------
+// double, float: every velocity row [N] in that precision.
+// Bf16Tail: the FP32 form, except that the rows of the far velocity tails
+// (fixed at set-up) hold BF16.  P.rows[i] is the byte offset of row i inside
+// each state array, with bit 0 set for a BF16 row.  The stencil arithmetic
+// and the stored face values are FP32 as in the FP32 form.  Values are
+// rounded to FP32 and then, in a BF16 row, to BF16 (round to nearest even).
+struct Bf16Tail {};
+
+template <typename ST>
+struct StoreT {
+    using C = ST;  // stencil arithmetic and stored face values
+    using R = ST;  // a loaded state value, as held in registers until used
+    static constexpr bool MIXED = false;
+};
+template <>
+struct StoreT<Bf16Tail> {
+    using C = float;
+    using R = unsigned;  // raw bits: the FP32 word, or the BF16 half zero-extended
+    static constexpr bool MIXED = true;
+};
+
+// row word of velocity i (uniform: a scalar load)
+__device__ __forceinline__ long long row_word(const Problem& P, int i) {
+    return ((const __attribute__((address_space(4))) long long*)(const void*)P.rows)[i];
+}
+
+// state value at (velocity i, cell c), raw until state_value converts it
+template <typename ST>
+__device__ __forceinline__ typename StoreT<ST>::R state_load(const Problem& P, const void* base, int i,
+                                                            long long c) {
+    if constexpr (StoreT<ST>::MIXED) {
+        const long long o = row_word(P, i);
+        const char* row = (const char*)base + (o & ~1LL);
+        if (o & 1) return (unsigned)((const unsigned short*)row)[c];
+        return ((const unsigned*)row)[c];
+    } else {
+        return ((const ST*)base)[(long long)i * P.N + c];
+    }
+}
+template <typename ST>
+__device__ __forceinline__ double state_value(const Problem& P, int i, typename StoreT<ST>::R r) {
+    if constexpr (StoreT<ST>::MIXED) {
+        return (double)__uint_as_float((row_word(P, i) & 1) ? r << 16 : r);
+    } else {
+        return (double)r;
+    }
+}
+template <typename ST>
+__device__ __forceinline__ double state_ld(const Problem& P, const void* base, int i, long long c) {
+    return state_value<ST>(P, i, state_load<ST>(P, base, i, c));
+}
+// the value a store of v at velocity i keeps
+template <typename ST>
+__device__ __forceinline__ double state_round(const Problem& P, int i, double v) {
+    if constexpr (StoreT<ST>::MIXED) {
+        const float f = (float)v;
+        return (row_word(P, i) & 1) ? (double)(float)(__bf16)f : (double)f;
+    } else {
+        return (double)(ST)v;
+    }
+}
+template <typename ST, bool STREAM>
+__device__ __forceinline__ void state_st(const Problem& P, void* base, int i, long long c, double v) {
+    if constexpr (StoreT<ST>::MIXED) {
+        const long long o = row_word(P, i);
+        char* row = (char*)base + (o & ~1LL);
+        const float f = (float)v;
+        if (o & 1) {
+            const unsigned short h = __builtin_bit_cast(unsigned short, (__bf16)f);
+            if constexpr (STREAM) __builtin_nontemporal_store(h, (unsigned short*)row + c);
+            else ((unsigned short*)row)[c] = h;
+        } else {
+            if constexpr (STREAM) __builtin_nontemporal_store(f, (float*)row + c);
+            else ((float*)row)[c] = f;
+        }
+    } else {
+        if constexpr (STREAM) st_stream<ST>(base, (long long)i * P.N + c, v);
+        else st<ST>(base, (long long)i * P.N + c, v);
+    }
+}
+
+// The fields of velocity i at NS source cells of one thread, with a single
+// format branch per velocity (the row kind is uniform); raw until slot_value.
+template <typename ST, int NS>
+__device__ __forceinline__ void load_slots(const Problem& P, const void* sg, const void* sb, int i,
+                                           const long long (&src)[NS], typename StoreT<ST>::R (&og)[NS],
+                                           typename StoreT<ST>::R (&ob)[NS]) {
+    if constexpr (StoreT<ST>::MIXED) {
+        const long long o = row_word(P, i);
+        const char* rg = (const char*)sg + (o & ~1LL);
+        const char* rb = (const char*)sb + (o & ~1LL);
+        if (o & 1) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                og[k] = ((const unsigned short*)rg)[src[k]];
+                ob[k] = ((const unsigned short*)rb)[src[k]];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                og[k] = ((const unsigned*)rg)[src[k]];
+                ob[k] = ((const unsigned*)rb)[src[k]];
+            }
+        }
+    } else {
+        const long long vb = (long long)i * P.N;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            og[k] = ((const ST*)sg)[vb + src[k]];
+            ob[k] = ((const ST*)sb)[vb + src[k]];
+        }
+    }
+}
+// value of a raw slot; shift = 16 for a BF16 row, else 0 (uniform)
+template <typename ST>
+__device__ __forceinline__ double slot_value(typename StoreT<ST>::R r, unsigned shift) {
+    if constexpr (StoreT<ST>::MIXED) return (double)__uint_as_float(r << shift);
+    else return (double)r;
+}
+
+// Access within one velocity row whose kind is known at compile time: `off`
+// is the element offset i N of the row (double, float) or its byte offset
+// (Bf16Tail, H: the row holds BF16).
+template <typename ST, bool H>
+__device__ __forceinline__ double row_ld(const void* base, long long off, long long c) {
+    if constexpr (StoreT<ST>::MIXED) {
+        const char* row = (const char*)base + off;
+        if constexpr (H) return (double)(float)((const __bf16*)row)[c];
+        else return (double)((const float*)row)[c];
+    } else {
+        return (double)((const ST*)base)[off + c];
+    }
+}
+template <typename ST, bool H>
+__device__ __forceinline__ double row_round(double v) {
+    if constexpr (StoreT<ST>::MIXED) {
+        if constexpr (H) return (double)(float)(__bf16)(float)v;
+        else return (double)(float)v;
+    } else {
+        return (double)(ST)v;
+    }
+}
+template <typename ST, bool H>
+__device__ __forceinline__ void row_st_stream(void* base, long long off, long long c, double v) {
+    if constexpr (StoreT<ST>::MIXED) {
+        char* row = (char*)base + off;
+        if constexpr (H) {
+            const unsigned short h = __builtin_bit_cast(unsigned short, (__bf16)(float)v);
+            __builtin_nontemporal_store(h, (unsigned short*)row + c);
+        } else {
+            __builtin_nontemporal_store((float)v, (float*)row + c);
+        }
+    } else {
+        st_stream<ST>(base, off + c, v);
+    }
+}
 
 // ---------------------------------------------------------------------------
 // primitives shared by the per-cell and per-face closures (Sec. 2)
@@ -188,8 +349,8 @@ __global__ __launch_bounds__(WG) void k_init_phi(Problem P) {
     }
     double geq = Pc[PC_A * N + c] * exp(-c2 * Pc[PC_INV2RT * N + c]);
     double beq = (ve[VE_HX2] + Pc[PC_CRT2 * N + c]) * geq;
-    st<ST>(const_cast<void*>(P.g_in), idx, geq);
-    st<ST>(const_cast<void*>(P.b_in), idx, beq);
+    state_st<ST, false>(P, const_cast<void*>(P.g_in), (int)i, c, geq);
+    state_st<ST, false>(P, const_cast<void*>(P.b_in), (int)i, c, beq);
 }
 
 // ---------------------------------------------------------------------------
@@ -321,9 +482,9 @@ __global__ __launch_bounds__(256) void k_init_quarter(Problem P) {
     }
     const double geq = k.A * exp(-c2 * k.inv2RT);
     double qg, qb;
-    quarter_step_eq<D>(k, v, geq, ld<ST>(P.g_in, idx), ld<ST>(P.b_in, idx), qg, qb);
-    st<ST>(P.qg, idx, qg);
-    st<ST>(P.qb, idx, qb);
+    quarter_step_eq<D>(k, v, geq, state_ld<ST>(P, P.g_in, (int)i, c), state_ld<ST>(P, P.b_in, (int)i, c), qg, qb);
+    state_st<ST, false>(P, P.qg, (int)i, c, qg);
+    state_st<ST, false>(P, P.qb, (int)i, c, qb);
 }
 
 // Value of phi_bar at a face centre at t_{n+1/2} from the upwind cell u,
@@ -459,7 +620,8 @@ struct FaceSumKernel {
     using G = Geo<D>;
     // stencil arithmetic (quarter-step values in LDS, limiters, face values) in
     // the storage precision; equilibria and the velocity sums stay FP64
-    using CT = ST;
+    using CT = typename StoreT<ST>::C;
+    using RT = typename StoreT<ST>::R;
     static constexpr int NT = G::TX * G::TY * G::TZ;
     // q-box points per thread: slot 0 is the thread's own cell, the other
     // slots cover the halo
@@ -503,7 +665,7 @@ struct FaceSumKernel {
     }
     // slope-box points outside the tile, and passes over them
     static constexpr int NARING = G::NA - NT;
-    static constexpr int NRING = (NARING + WG - 1) / WG;
+    static constexpr int NRING2 = (2 * NARING + WG - 1) / WG;  // (point, field) passes
 
     // when the q-box points do not fit in registers, the cell coefficients
     // of the whole box are staged in LDS once (3-D FP32; the FP64 3-D box does
@@ -622,16 +784,11 @@ struct FaceSumKernel {
         // the compiler wait for every outstanding memory operation, the face
         // value stores included.
         constexpr bool PREFETCH = NSLOT <= 2 || QS;
-        const ST* const src_g = reinterpret_cast<const ST*>(QS ? P.qg : P.g_in);
-        const ST* const src_b = reinterpret_cast<const ST*>(QS ? P.qb : P.b_in);
-        ST pa_g[NSLOT], pa_b[NSLOT], pb_g[NSLOT], pb_b[NSLOT];
+        const void* const src_g = QS ? P.qg : P.g_in;
+        const void* const src_b = QS ? P.qb : P.b_in;
+        RT pa_g[NSLOT], pa_b[NSLOT], pb_g[NSLOT], pb_b[NSLOT];
         if constexpr (PREFETCH) {
-#pragma unroll
-            for (int k = 0; k < NSLOT; ++k) {
-                const long long a0 = (long long)(v0 < v1 ? v0 : 0) * N + srcq[k];
-                pa_g[k] = src_g[a0];
-                pa_b[k] = src_b[a0];
-            }
+            load_slots<ST, NSLOT>(P, src_g, src_b, v0 < v1 ? v0 : 0, srcq, pa_g, pa_b);
         }
         const long long fstride = P.fv_stride;  // per (d, field) block of FV
 
@@ -648,8 +805,8 @@ struct FaceSumKernel {
         int ix = v0 % nvx;
 
         // one velocity: cur_* hold its prefetched fields, nxt_* receive the next
-        auto velocity = [&](int i, int buf, ST(&cur_g)[NSLOT], ST(&cur_b)[NSLOT], ST(&nxt_g)[NSLOT],
-                            ST(&nxt_b)[NSLOT]) __attribute__((always_inline)) {
+        auto velocity = [&](int i, int buf, RT(&cur_g)[NSLOT], RT(&cur_b)[NSLOT], RT(&nxt_g)[NSLOT],
+                            RT(&nxt_b)[NSLOT]) __attribute__((always_inline)) {
             const Vel v = load_vel(P.vel, i);
             if constexpr (WALKER) {
                 if (i == v0 || ix % WALK == 0) {
@@ -662,7 +819,8 @@ struct FaceSumKernel {
                         for (int k = 0; k < NSLOT; ++k) wq[k].advance();
                 }
             }
-            const long long vb = (long long)i * N;
+            // BF16 rows: the raw halves move to the top of an FP32 word
+            const unsigned shift = StoreT<ST>::MIXED ? (unsigned)(row_word(P, i) & 1) << 4 : 0u;
             CT* const sq0 = sm.q[buf][0];
             CT* const sq1 = sm.q[buf][1];
             CT* const sa0 = sm.a[buf][0];
@@ -671,12 +829,7 @@ struct FaceSumKernel {
             if constexpr (PREFETCH) {
                 // unconditional loads (the last velocity re-reads itself) keep
                 // the wait counts exact
-                const long long nb = i + 1 < v1 ? vb + N : vb;
-#pragma unroll
-                for (int k = 0; k < NSLOT; ++k) {
-                    nxt_g[k] = src_g[nb + srcq[k]];
-                    nxt_b[k] = src_b[nb + srcq[k]];
-                }
+                load_slots<ST, NSLOT>(P, src_g, src_b, i + 1 < v1 ? i + 1 : i, srcq, nxt_g, nxt_b);
             }
 
             // stage 1: quarter-step fields on the q box
@@ -686,11 +839,11 @@ struct FaceSumKernel {
                     const int r = lq[k] & 0xFFFFF;
                     double g, b;
                     if constexpr (PREFETCH) {
-                        g = (double)cur_g[k];
-                        b = (double)cur_b[k];
+                        g = slot_value<ST>(cur_g[k], shift);
+                        b = slot_value<ST>(cur_b[k], shift);
                     } else {
-                        g = (double)src_g[vb + srcq[k]];
-                        b = (double)src_b[vb + srcq[k]];
+                        g = state_ld<ST>(P, src_g, i, srcq[k]);
+                        b = state_ld<ST>(P, src_b, i, srcq[k]);
                     }
                     double qg, qb;
                     if constexpr (QS) {
@@ -745,22 +898,24 @@ struct FaceSumKernel {
                     }
                 }
             }
+            // the ring: one (point, field) pair per thread and pass, so the
+            // work spreads over all waves of the workgroup
 #pragma unroll
-            for (int k = 0; k < NRING; ++k) {
-                const int h = tid + k * WG;
-                if (h < NARING) {
+            for (int k = 0; k < NRING2; ++k) {
+                const int t = tid + k * WG;
+                if (t < 2 * NARING) {
+                    const int f = t >= NARING;
+                    const int h = t - f * NARING;
                     const int p = slope_ring_point(h);
                     const int px = p % G::AX, py = (p / G::AX) % G::AY, pz = p / (G::AX * G::AY);
                     const int qi = (px + 1) + G::QX * ((py + (D >= 2 ? 1 : 0)) + G::QY * (pz + (D >= 3 ? 1 : 0)));
+                    const CT* q = sq0 + f * G::NQ;
+                    CT* a = sa0 + f * (D * G::NA);
+                    const CT c = q[qi];
 #pragma unroll
                     for (int e = 0; e < D; ++e) {
                         const int sq = G::SQ(e);
-#pragma unroll
-                        for (int f = 0; f < 2; ++f) {
-                            const CT* q = f == 0 ? sq0 : sq1;
-                            const CT c = q[qi];
-                            (f == 0 ? sa0 : sa1)[e * G::NA + p] = half_van_leer(c - q[qi - sq], q[qi + sq] - c);
-                        }
+                        a[e * G::NA + p] = half_van_leer(c - q[qi - sq], q[qi + sq] - c);
                     }
                 }
             }
@@ -807,8 +962,8 @@ struct FaceSumKernel {
                 const double vg = fv[0], vb2 = fv[1];
                 if (fvalid[d]) {
                     const long long o = (long long)(2 * d) * fstride + (long long)i * NE + fe;
-                    st_stream<ST>(P.FV, o, vg);
-                    st_stream<ST>(P.FV, o + fstride, vb2);
+                    st_stream<CT>(P.FV, o, vg);
+                    st_stream<CT>(P.FV, o + fstride, vb2);
                 }
                 // weighted velocity products come from the table (uniform)
                 const const_dptr vp = vel_ptr(P.vel, i);
@@ -842,7 +997,7 @@ struct FaceSumKernel {
         } else {
             // 3-D: registers allow one set; the copy costs a wait per velocity
             for (int i = v0; i < v1; ++i) {
-                ST cg[NSLOT], cb[NSLOT];
+                RT cg[NSLOT], cb[NSLOT];
 #pragma unroll
                 for (int k = 0; k < NSLOT; ++k) {
                     cg[k] = pa_g[k];
@@ -871,6 +1026,7 @@ struct FaceSumKernel {
 // ---------------------------------------------------------------------------
 template <int D, typename ST>
 struct UpdateKernel {
+    using CT = typename StoreT<ST>::C;  // stored face values
     __device__ static void run(const Problem& P, long long c, int slice, int nslices) {
         const long long N = P.N, NE = P.NE;
         const bool inside = c < N;
@@ -915,7 +1071,7 @@ struct UpdateKernel {
         // 1-D and 2-D.  The 3-D kernel has no registers to spare, and the FP32
         // kernel runs a third wave per SIMD without the recurrence state,
         // which outweighs the exponentials it saves.
-        constexpr bool WALKER = D <= 2 && sizeof(ST) == 8;
+        constexpr bool WALKER = D <= 2 && std::is_same<ST, double>::value;
         const double h = P.hxi0;
         const int nvx = P.nv[0];
         GaussWalk w0, w1, wl[D], wr[D];
@@ -930,86 +1086,141 @@ struct UpdateKernel {
         }
         int ix = v0 % nvx;
 
-        // FP64 without the recurrence: two velocities per trip (twice the
-        // loads in flight per wave)
-        constexpr int UNROLL = sizeof(ST) == 8 && !WALKER ? 2 : 1;
-#pragma unroll UNROLL
-        for (int i = v0; i < v1; ++i) {
-            const Vel v = load_vel(P.vel, i);
-            if constexpr (WALKER) {
-                if (i == v0 || ix % WALK == 0) {
-                    const int a0 = ix - ix % WALK;
-                    // a slice starting inside a block walks from its anchor
-                    const Vel va = a0 == ix ? v : load_vel(P.vel, i - (ix - a0));
-                    w0.anchor<D>(k0.A, k0.inv2RT, k0.u, va, h);
-                    w1.anchor<D>(k1.A, k1.inv2RT, k1.u, va, h);
-#pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        wl[d].template anchor<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, va, h);
-                        wr[d].template anchor<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, va, h);
-                    }
-                    for (int j = a0; j < ix; ++j) {
-                        w0.advance();
-                        w1.advance();
-#pragma unroll
+        if constexpr (!StoreT<ST>::MIXED) {
+            // FP64 without the recurrence: two velocities per trip (twice the
+            // loads in flight per wave)
+            constexpr int UNROLL = std::is_same<ST, double>::value && !WALKER ? 2 : 1;
+    #pragma unroll UNROLL
+            for (int i = v0; i < v1; ++i) {
+                const Vel v = load_vel(P.vel, i);
+                if constexpr (WALKER) {
+                    if (i == v0 || ix % WALK == 0) {
+                        const int a0 = ix - ix % WALK;
+                        // a slice starting inside a block walks from its anchor
+                        const Vel va = a0 == ix ? v : load_vel(P.vel, i - (ix - a0));
+                        w0.anchor<D>(k0.A, k0.inv2RT, k0.u, va, h);
+                        w1.anchor<D>(k1.A, k1.inv2RT, k1.u, va, h);
+    #pragma unroll
                         for (int d = 0; d < D; ++d) {
-                            wl[d].advance();
-                            wr[d].advance();
+                            wl[d].template anchor<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, va, h);
+                            wr[d].template anchor<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, va, h);
+                        }
+                        for (int j = a0; j < ix; ++j) {
+                            w0.advance();
+                            w1.advance();
+    #pragma unroll
+                            for (int d = 0; d < D; ++d) {
+                                wl[d].advance();
+                                wr[d].advance();
+                            }
                         }
                     }
                 }
-            }
-            const long long vb = (long long)i * N;
-            const double g = ld<ST>(P.g_in, vb + cc);
-            const double b = ld<ST>(P.b_in, vb + cc);
-            double Fg = 0.0, Fb = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                const long long o = (long long)(2 * d) * fstride + (long long)i * NE;
-                const double eql = WALKER ? wl[d].template value<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v)
-                                          : maxwellian<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v);
-                const double eqr = WALKER ? wr[d].template value<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v)
-                                          : maxwellian<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v);
-                double gl, bl, gr, br;
-                fcl[d].invert(v, eql, ld<ST>(P.FV, o + fl[d]), ld<ST>(P.FV, o + fstride + fl[d]), gl, bl);
-                fcr[d].invert(v, eqr, ld<ST>(P.FV, o + fr[d]), ld<ST>(P.FV, o + fstride + fr[d]), gr, br);
-                const double sxd = v.xi[d] * P.inv_dx[d];
-                Fg += sxd * (gr - gl);
-                Fb += sxd * (br - bl);
-            }
-            double xu0 = 0.0;
-#pragma unroll
-            for (int d = 0; d < D; ++d) xu0 += v.xi[d] * k0.u[d];
-            const double geq0 = WALKER ? w0.value<D>(k0.A, k0.inv2RT, k0.u, v) : maxwellian<D>(k0.A, k0.inv2RT, k0.u, v);
-            const double beq0 = (v.hx2 + k0.cRT2) * geq0;
-            const double geq1 = WALKER ? w1.value<D>(k1.A, k1.inv2RT, k1.u, v) : maxwellian<D>(k1.A, k1.inv2RT, k1.u, v);
-            const double beq1 = (v.hx2 + k1.cRT2) * geq1;
-            const double Z0 = xu0 - k0.hu2;
-            // eq. phiupdate with dt/(2 tau) = 2 beta and dt S_b = 4 eta Z (g - g_eq)
-            const double gn = (g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg) * inv_g;
-            const double bn = (b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
-                               4.0 * k0.eta * Z0 * (g - geq0)) *
-                              inv_b;
-            if (inside) {
-                st_stream<ST>(P.g_out, vb + cc, gn);
-                st_stream<ST>(P.b_out, vb + cc, bn);
-                if constexpr (quarter_stored(D)) {
-                    // next step's phi_bar_plus from the state as stored
-                    double qg, qb;
-                    quarter_step_eq<D>(k1, v, geq1, (double)(ST)gn, (double)(ST)bn, qg, qb);
-                    st_stream<ST>(P.qg, vb + cc, qg);
-                    st_stream<ST>(P.qb, vb + cc, qb);
+                const long long vb = (long long)i * N;
+                const double g = ld<ST>(P.g_in, vb + cc);
+                const double b = ld<ST>(P.b_in, vb + cc);
+                double Fg = 0.0, Fb = 0.0;
+    #pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const long long o = (long long)(2 * d) * fstride + (long long)i * NE;
+                    const double eql = WALKER ? wl[d].template value<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v)
+                                              : maxwellian<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v);
+                    const double eqr = WALKER ? wr[d].template value<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v)
+                                              : maxwellian<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v);
+                    double gl, bl, gr, br;
+                    fcl[d].invert(v, eql, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl, bl);
+                    fcr[d].invert(v, eqr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr, br);
+                    const double sxd = v.xi[d] * P.inv_dx[d];
+                    Fg += sxd * (gr - gl);
+                    Fb += sxd * (br - bl);
+                }
+                double xu0 = 0.0;
+    #pragma unroll
+                for (int d = 0; d < D; ++d) xu0 += v.xi[d] * k0.u[d];
+                const double geq0 = WALKER ? w0.value<D>(k0.A, k0.inv2RT, k0.u, v) : maxwellian<D>(k0.A, k0.inv2RT, k0.u, v);
+                const double beq0 = (v.hx2 + k0.cRT2) * geq0;
+                const double geq1 = WALKER ? w1.value<D>(k1.A, k1.inv2RT, k1.u, v) : maxwellian<D>(k1.A, k1.inv2RT, k1.u, v);
+                const double beq1 = (v.hx2 + k1.cRT2) * geq1;
+                const double Z0 = xu0 - k0.hu2;
+                // eq. phiupdate with dt/(2 tau) = 2 beta and dt S_b = 4 eta Z (g - g_eq)
+                const double gn = (g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg) * inv_g;
+                const double bn = (b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
+                                   4.0 * k0.eta * Z0 * (g - geq0)) *
+                                  inv_b;
+                if (inside) {
+                    st_stream<ST>(P.g_out, vb + cc, gn);
+                    st_stream<ST>(P.b_out, vb + cc, bn);
+                    if constexpr (quarter_stored(D)) {
+                        // next step's phi_bar_plus from the state as stored
+                        double qg, qb;
+                        quarter_step_eq<D>(k1, v, geq1, (double)(ST)gn, (double)(ST)bn, qg, qb);
+                        st_stream<ST>(P.qg, vb + cc, qg);
+                        st_stream<ST>(P.qb, vb + cc, qb);
+                    }
+                }
+                if constexpr (WALKER) {
+                    w0.advance();
+                    w1.advance();
+    #pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        wl[d].advance();
+                        wr[d].advance();
+                    }
+                    if (++ix == nvx) ix = 0;
                 }
             }
-            if constexpr (WALKER) {
-                w0.advance();
-                w1.advance();
+        } else {
+            // BF16-tail form: the row kind is uniform, so each velocity takes
+            // one branch into a copy of the body specialised for FP32 or BF16
+            // rows (one straight-line body per kind schedules its loads as
+            // well as the FP32 form does); no recurrence for the equilibria
+            auto one = [&](int i, long long off, auto half) __attribute__((always_inline)) {
+                constexpr bool H = decltype(half)::value;
+                const Vel v = load_vel(P.vel, i);
+                const double g = row_ld<ST, H>(P.g_in, off, cc);
+                const double b = row_ld<ST, H>(P.b_in, off, cc);
+                double Fg = 0.0, Fb = 0.0;
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    wl[d].advance();
-                    wr[d].advance();
+                    const long long fo = (long long)(2 * d) * fstride + (long long)i * NE;
+                    const double eql = maxwellian<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v);
+                    const double eqr = maxwellian<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v);
+                    double gl, bl, gr, br;
+                    fcl[d].invert(v, eql, ld<CT>(P.FV, fo + fl[d]), ld<CT>(P.FV, fo + fstride + fl[d]), gl, bl);
+                    fcr[d].invert(v, eqr, ld<CT>(P.FV, fo + fr[d]), ld<CT>(P.FV, fo + fstride + fr[d]), gr, br);
+                    const double sxd = v.xi[d] * P.inv_dx[d];
+                    Fg += sxd * (gr - gl);
+                    Fb += sxd * (br - bl);
                 }
-                if (++ix == nvx) ix = 0;
+                double xu0 = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) xu0 += v.xi[d] * k0.u[d];
+                const double geq0 = maxwellian<D>(k0.A, k0.inv2RT, k0.u, v);
+                const double beq0 = (v.hx2 + k0.cRT2) * geq0;
+                const double geq1 = maxwellian<D>(k1.A, k1.inv2RT, k1.u, v);
+                const double beq1 = (v.hx2 + k1.cRT2) * geq1;
+                const double Z0 = xu0 - k0.hu2;
+                // eq. phiupdate, as in the plain forms
+                const double gn = (g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg) * inv_g;
+                const double bn = (b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
+                                   4.0 * k0.eta * Z0 * (g - geq0)) *
+                                  inv_b;
+                if (inside) {
+                    row_st_stream<ST, H>(P.g_out, off, cc, gn);
+                    row_st_stream<ST, H>(P.b_out, off, cc, bn);
+                    if constexpr (quarter_stored(D)) {
+                        // next step's phi_bar_plus from the state as stored
+                        double qg, qb;
+                        quarter_step_eq<D>(k1, v, geq1, row_round<ST, H>(gn), row_round<ST, H>(bn), qg, qb);
+                        row_st_stream<ST, H>(P.qg, off, cc, qg);
+                        row_st_stream<ST, H>(P.qb, off, cc, qb);
+                    }
+                }
+            };
+            for (int i = v0; i < v1; ++i) {
+                const long long o = row_word(P, i);
+                if (o & 1) one(i, o & ~1LL, std::true_type{});
+                else one(i, o, std::false_type{});
             }
         }
     }
@@ -1038,12 +1249,31 @@ __global__ __launch_bounds__(WG, face_sum_waves<D>()) void k_face_sums(Problem P
 // its next one starts after this one), so no memset enters a graph.
 // Problems of different dimension share the launch; LDS is the union of their
 // needs.
+// The item index is uniform across the workgroup; readfirstlane tells the
+// compiler so, and the item and its problem descriptor are then read through
+// the constant address space: scalar loads into SGPRs instead of a copy of
+// the descriptor in vector registers (the FP32 1-D/2-D face-sum class then
+// runs 3 waves per SIMD, like the single-problem kernel).  Forcing the update
+// class to 3 waves as well spills registers and is slower.
 __device__ __forceinline__ int next_item(int* queue, int* slot) {
     if (threadIdx.x == 0) *slot = atomicAdd(queue, 1);
     __syncthreads();
-    const int w = *slot;
+    const int w = __builtin_amdgcn_readfirstlane(*slot);
     __syncthreads();  // every thread has read the slot before it is refilled
     return w;
+}
+
+// word-wise copy of a uniform descriptor through the constant address space
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "descriptor size");
+    typedef const __attribute__((address_space(4))) unsigned* const_uptr;
+    const const_uptr s = (const_uptr)(const void*)p;
+    T r;
+    unsigned* d = reinterpret_cast<unsigned*>(&r);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) d[k] = s[k];
+    return r;
 }
 
 template <typename ST, int MAXD, bool DIR>
@@ -1057,8 +1287,8 @@ __global__ __launch_bounds__(WG) void k_face_sums_batched(const Problem* probs, 
     __shared__ int slot;
     if (blockIdx.x == 0 && threadIdx.x == 0) *other = 0;
     for (int w = next_item(queue, &slot); w < nitems; w = next_item(queue, &slot)) {
-        const WorkItem it = items[w];
-        const Problem P = probs[it.prob];
+        const WorkItem it = load_uniform(items + w);
+        const Problem P = load_uniform(probs + it.prob);
         if (P.D == 1) FaceSumKernel<1, ST, DIR>::run(P, it.tile, it.slice, P.nslices, sm.s1);
         else if (MAXD >= 2 && P.D == 2)
             FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR>::run(P, it.tile, it.slice, P.nslices, sm.s2);
@@ -1082,8 +1312,8 @@ __global__ __launch_bounds__(WG) void k_update_batched(const Problem* probs, con
     __shared__ int slot;
     if (blockIdx.x == 0 && threadIdx.x == 0) *other = 0;
     for (int w = next_item(queue, &slot); w < nitems; w = next_item(queue, &slot)) {
-        const WorkItem it = items[w];
-        const Problem P = probs[it.prob];
+        const WorkItem it = load_uniform(items + w);
+        const Problem P = load_uniform(probs + it.prob);
         const long long c = (long long)it.tile * WG + threadIdx.x;
         if (P.D == 1) UpdateKernel<1, ST>::run(P, c, it.slice, P.nslices_upd);
         else if (MAXD >= 2 && P.D == 2) UpdateKernel<MAXD >= 2 ? 2 : 1, ST>::run(P, c, it.slice, P.nslices_upd);
@@ -1256,8 +1486,7 @@ __global__ __launch_bounds__(WG) void k_face_close_batched(const Problem* probs,
     long long g = (long long)blockIdx.x * WG + threadIdx.x;
     if (g >= total) return;
     int p = find_problem(offsets, nprob, g);
-    const Problem P = probs[p];
-    face_close_one(P, g - offsets[p]);
+    face_close_one(probs[p], g - offsets[p]);  // by reference: no private copy
 }
 
 __global__ __launch_bounds__(WG) void k_cell_close_batched(const Problem* probs, const long long* offsets,
@@ -1265,8 +1494,7 @@ __global__ __launch_bounds__(WG) void k_cell_close_batched(const Problem* probs,
     long long g = (long long)blockIdx.x * WG + threadIdx.x;
     if (g >= total) return;
     int p = find_problem(offsets, nprob, g);
-    const Problem P = probs[p];
-    cell_close_one(P, g - offsets[p]);
+    cell_close_one(probs[p], g - offsets[p]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1290,10 +1518,13 @@ __global__ __launch_bounds__(WG) void k_moments(Problem P, const double* W, doub
     T[c] = (P.gamma - 1.0) / P.R * (Wv[D + 1] / r - 0.5 * u2);
 }
 
+// a state array ([V][N] in the problem's storage form) as FP64
 template <typename ST>
-__global__ __launch_bounds__(WG) void k_to_f64(long long n, const void* src, double* dst) {
-    long long i = (long long)blockIdx.x * WG + threadIdx.x;
-    if (i < n) dst[i] = ld<ST>(src, i);
+__global__ __launch_bounds__(WG) void k_to_f64(Problem P, const void* src, double* dst) {
+    const long long idx = (long long)blockIdx.x * WG + threadIdx.x;
+    if (idx >= P.N * P.V) return;
+    const long long i = idx / P.N;
+    dst[idx] = state_ld<ST>(P, src, (int)i, idx - i * P.N);
 }
 
 // ---------------------------------------------------------------------------
@@ -1309,20 +1540,24 @@ static inline unsigned blocks_for(long long n) { return (unsigned)((n + WG - 1) 
             if ((DIM) == 1) MACRO(1, double);                        \
             else if ((DIM) == 2) MACRO(2, double);                   \
             else MACRO(3, double);                                   \
-        } else {                                                     \
+        } else if ((STORAGE) == 1) {                                 \
             if ((DIM) == 1) MACRO(1, float);                         \
             else if ((DIM) == 2) MACRO(2, float);                    \
             else MACRO(3, float);                                    \
+        } else {                                                     \
+            if ((DIM) == 1) MACRO(1, Bf16Tail);                      \
+            else if ((DIM) == 2) MACRO(2, Bf16Tail);                 \
+            else MACRO(3, Bf16Tail);                                 \
         }                                                            \
     } while (0)
 
 hipError_t launch_init(const Problem& P, const double* rho, const double* u, const double* T,
                        hipStream_t s) {
     hipLaunchKernelGGL(k_init_cells, dim3(blocks_for(P.N)), dim3(WG), 0, s, P, rho, u, T);
-    if (P.storage == 0)
-        hipLaunchKernelGGL(k_init_phi<double>, dim3(blocks_for(P.N * P.V)), dim3(WG), 0, s, P);
-    else
-        hipLaunchKernelGGL(k_init_phi<float>, dim3(blocks_for(P.N * P.V)), dim3(WG), 0, s, P);
+    const dim3 gphi(blocks_for(P.N * P.V));
+    if (P.storage == 0) hipLaunchKernelGGL(k_init_phi<double>, gphi, dim3(WG), 0, s, P);
+    else if (P.storage == 1) hipLaunchKernelGGL(k_init_phi<float>, gphi, dim3(WG), 0, s, P);
+    else hipLaunchKernelGGL(k_init_phi<Bf16Tail>, gphi, dim3(WG), 0, s, P);
     if (quarter_stored(P.D)) {
         const dim3 grid(blocks_for(P.N * P.V));
 #define CDG_L(D, ST) hipLaunchKernelGGL((k_init_quarter<D, ST>), grid, dim3(256), 0, s, P)
@@ -1390,11 +1625,10 @@ hipError_t launch_moments(const Problem& P, const double* W, double* rho, double
 }
 
 hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStream_t s) {
-    long long n = P.N * P.V;
-    if (P.storage == 0)
-        hipLaunchKernelGGL(k_to_f64<double>, dim3(blocks_for(n)), dim3(WG), 0, s, n, src, dst);
-    else
-        hipLaunchKernelGGL(k_to_f64<float>, dim3(blocks_for(n)), dim3(WG), 0, s, n, src, dst);
+    const dim3 grid(blocks_for(P.N * P.V));
+    if (P.storage == 0) hipLaunchKernelGGL(k_to_f64<double>, grid, dim3(WG), 0, s, P, src, dst);
+    else if (P.storage == 1) hipLaunchKernelGGL(k_to_f64<float>, grid, dim3(WG), 0, s, P, src, dst);
+    else hipLaunchKernelGGL(k_to_f64<Bf16Tail>, grid, dim3(WG), 0, s, P, src, dst);
     return hipGetLastError();
 }
 
@@ -1404,10 +1638,14 @@ hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStre
             if ((MAXD) == 1) MACRO(double, 1);                       \
             else if ((MAXD) == 2) MACRO(double, 2);                  \
             else MACRO(double, 3);                                   \
-        } else {                                                     \
+        } else if ((STORAGE) == 1) {                                 \
             if ((MAXD) == 1) MACRO(float, 1);                        \
             else if ((MAXD) == 2) MACRO(float, 2);                   \
             else MACRO(float, 3);                                    \
+        } else {                                                     \
+            if ((MAXD) == 1) MACRO(Bf16Tail, 1);                     \
+            else if ((MAXD) == 2) MACRO(Bf16Tail, 2);                \
+            else MACRO(Bf16Tail, 3);                                 \
         }                                                            \
     } while (0)
 

@@ -231,10 +231,10 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
     b->cell_total = ct;
     // work lists per class (index 2 storage + Dirichlet), sorted by estimated
     // cost (largest first)
-    constexpr int NCLASS = 4;
+    constexpr int NCLASS = 6;  // 3 storage forms x (with, without Dirichlet sides)
     std::vector<std::vector<WorkItem>> fs(NCLASS), up(NCLASS);
     std::vector<std::vector<double>> cfs(NCLASS), cup(NCLASS);
-    int maxd[NCLASS] = {0, 0, 0, 0};
+    int maxd[NCLASS] = {0, 0, 0, 0, 0, 0};
     auto class_of = [](const Resolved& r) { return 2 * r.storage + (r.any_dirichlet ? 1 : 0); };
     for (int j = 0; j < count; ++j) {
         const Resolved& r = ctxs[j]->r;
