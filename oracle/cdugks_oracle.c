@@ -20,6 +20,8 @@
  *   - face slope sigma_f = sigma(u) + delta * t_{d,.}(u) with t the limited
  *     derivative along the face normal d of the slope vector, and the foot
  *     value phi_bar_plus(x_f) - h xi . sigma_f (the printed formula is garbled);
+ *     the single-slope option drops step 4 and takes sigma_f = sigma(u), the
+ *     classic upwind reconstruction phi_bar_plus(x_u) + (x_f - h xi - x_u) . sigma(u);
  *   - W^{n+1} = W^n - dt/|V| * sum of outward flux moments (the sign printed
  *     in eq. rhoupdate is inconsistent with eqs. implicit and phiupdate);
  *   - the source integral in the energy update is zero when a = 0;
@@ -250,6 +252,7 @@ oracle_state* oracle_create(const oracle_params* p)
     if (p->dim < 1 || p->dim > 3) return NULL;
     if (!(p->gamma > 1.0) || p->gamma > 5.0 / 3.0 + 1e-12) return NULL;
     if (!(p->Pr > 0.0) || !(p->R > 0.0) || !(p->dt > 0.0)) return NULL;
+    if (p->reconstruction != ORC_RECON_SLOPES_OF_SLOPES && p->reconstruction != ORC_RECON_SINGLE_SLOPE) return NULL;
     oracle_state* s = (oracle_state*)calloc(1, sizeof *s);
     if (!s) return NULL;
     s->p = *p;
@@ -450,8 +453,10 @@ static int one_step(oracle_state* s)
      *    component of the gradients, computed like the gradients). */
     double* ttg = (double*)calloc((size_t)NE * D * D * V, sizeof(double));
     double* ttb = (double*)calloc((size_t)NE * D * D * V, sizeof(double));
+    const int single_slope = s->p.reconstruction == ORC_RECON_SINGLE_SLOPE;
 #pragma omp parallel for schedule(static)
     for (long e = 0; e < NE; ++e) {
+        if (single_slope) continue;  /* not used */
         long c[3];
         ext_coords(s, e, c);
         int inside = 1;
@@ -527,8 +532,12 @@ static int one_step(oracle_state* s)
                     double fg = qg[eu * V + i] + delta * sgg[(eu * D + d) * V + i];
                     double fb = qb[eu * V + i] + delta * sgb[(eu * D + d) * V + i];
                     for (int k = 0; k < D; ++k) {
-                        double sfg = sgg[(eu * D + k) * V + i] + delta * ttg[((eu * D + d) * D + k) * V + i];
-                        double sfb = sgb[(eu * D + k) * V + i] + delta * ttb[((eu * D + d) * D + k) * V + i];
+                        double sfg = sgg[(eu * D + k) * V + i];
+                        double sfb = sgb[(eu * D + k) * V + i];
+                        if (single_slope == 0) {  /* face gradient reconstructed too */
+                            sfg += delta * ttg[((eu * D + d) * D + k) * V + i];
+                            sfb += delta * ttb[((eu * D + d) * D + k) * V + i];
+                        }
                         fg -= h * xi[k] * sfg;
                         fb -= h * xi[k] * sfb;
                     }

@@ -24,6 +24,7 @@ extern "C" {
 enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_DIRICHLET = 2 };
 enum { ORC_QUAD_TRAPEZOID = 0, ORC_QUAD_BOOLE = 1 };
 enum { ORC_RELAX_MU = 0, ORC_RELAX_TAU = 1 };
+enum { ORC_RECON_SLOPES_OF_SLOPES = 0, ORC_RECON_SINGLE_SLOPE = 1 };
 
 typedef struct {
     int dim;              /* D = 1, 2 or 3 */
@@ -43,6 +44,12 @@ typedef struct {
     double mu_ref, T_ref, omega;
     double tau;
     double dt;            /* time step */
+    int reconstruction;   /* ORC_RECON_SLOPES_OF_SLOPES (the paper's Sec. 2.1:
+                             the face gradient is itself reconstructed from
+                             limited derivatives of the slopes) or
+                             ORC_RECON_SINGLE_SLOPE (the upwind cell's limited
+                             slopes alone carried to the foot of the
+                             characteristic) */
 } oracle_params;
 
 typedef struct oracle_state oracle_state;

@@ -21,6 +21,7 @@ LIB = os.path.join(HERE, "libcdugks_oracle.so")
 
 BC = {"periodic": 0, "outflow": 1, "dirichlet": 2}
 QUAD = {"trapezoid": 0, "boole": 1}
+RECON = {"slopes_of_slopes": 0, "single_slope": 1}
 
 
 def build(force: bool = True) -> str:
@@ -57,6 +58,7 @@ class _Params(ctypes.Structure):
         ("omega", ctypes.c_double),
         ("tau", ctypes.c_double),
         ("dt", ctypes.c_double),
+        ("reconstruction", ctypes.c_int),
     ]
 
 
@@ -133,7 +135,8 @@ class Oracle:
 
     ``prob`` is a dict with keys dim, n, lo, hi, bc (list of
     'periodic'/'outflow'/'dirichlet'), nv, vmin, vmax, quad, gamma, Pr, R,
-    relax ('mu' or 'tau'), mu_ref, T_ref, omega, tau, dt, and for Dirichlet
+    relax ('mu' or 'tau'), mu_ref, T_ref, omega, tau, dt, reconstruction
+    ('slopes_of_slopes', the paper's, or 'single_slope'), and for Dirichlet
     dimensions ``dirichlet[d] = [[rho, u_1..u_D, T] low side, [..] high side]``.
     """
 
@@ -174,6 +177,7 @@ class Oracle:
         tau = prob.get("tau")
         p.tau = math.inf if tau is None else float(tau)
         p.dt = float(prob["dt"])
+        p.reconstruction = RECON[prob.get("reconstruction", "slopes_of_slopes")]
         self._p = p
         self.D = D
         self.N = int(np.prod([prob["n"][d] for d in range(D)]))

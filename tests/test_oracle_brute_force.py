@@ -9,7 +9,8 @@ step that recomputed W from the distributions, dropped the S_b source, mixed
 up the upwind side, the ghost map, an axis, the cross terms of the slope
 reconstruction or the sign of the flux would miss the 50-digit result.
 The readings are those the oracle documents: Van Leer of the one-sided
-derivatives, face value q(u) + delta s_d(u) - h xi.(s(u) + delta t_d(u)),
+derivatives, face value q(u) + delta s_d(u) - h xi.(s(u) + delta t_d(u))
+(the single-slope option: q(u) + delta s_d(u) - h xi.s(u)),
 mean of the two one-sided values for xi_d = 0, outward-flux sign, zero
 source integral in the energy update, outflow ghosts clamp the index.
 """
@@ -59,6 +60,7 @@ class Brute:
         self.Pr = M(P["Pr"])
         self.dt = M(P["dt"])
         self.h = self.dt / 2
+        self.single_slope = P.get("reconstruction") == "single_slope"
 
     # ---- Sec. 2: primitives, relaxation times, equilibria ----
     def prim(self, W):
@@ -138,7 +140,10 @@ class Brute:
             side +1 (right) or -1 (left) along d."""
             delta = side * self.dx[d] / 2
             at_face = Q(f, ux, uy, i) + delta * slope(f, ux, uy, i, d)
-            sig = [slope(f, ux, uy, i, e) + delta * slope2(f, ux, uy, i, d, e) for e in range(2)]
+            if self.single_slope:  # the upwind cell's slopes carried to the foot
+                sig = [slope(f, ux, uy, i, e) for e in range(2)]
+            else:  # face gradient reconstructed from the slopes of the slopes
+                sig = [slope(f, ux, uy, i, e) + delta * slope2(f, ux, uy, i, d, e) for e in range(2)]
             return at_face - h * (self.xi[i][0] * sig[0] + self.xi[i][1] * sig[1])
 
         def face_bar(f, x, y, i, d):
@@ -227,12 +232,13 @@ class Brute:
         return g1, b1, W1
 
 
-@pytest.mark.parametrize("bc_y", ["outflow", "periodic"])
-def test_one_step_matches_50_digit_brute_force(bc_y):
+@pytest.mark.parametrize("bc_y,recon", [("outflow", "slopes_of_slopes"), ("periodic", "slopes_of_slopes"),
+                                         ("outflow", "single_slope")])
+def test_one_step_matches_50_digit_brute_force(bc_y, recon):
     orc.build(force=False)
     P = dict(dim=2, n=[4, 3], lo=[0.0, -0.5], hi=[1.0, 0.25], bc=["periodic", bc_y], nv=[3, 4],
              vmin=[-2.0, -1.5], vmax=[2.0, 2.5], quad="trapezoid", gamma=7.0 / 5.0, Pr=2.0 / 3.0, R=0.5,
-             relax="mu", mu_ref=0.02, T_ref=1.0, omega=0.5, dt=0.01)
+             relax="mu", mu_ref=0.02, T_ref=1.0, omega=0.5, dt=0.01, reconstruction=recon)
     N, V = 12, 12
     rng = np.random.default_rng(2208)
     # smooth-ish positive distributions with random perturbations, off

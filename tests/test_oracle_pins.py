@@ -19,6 +19,7 @@ transposed operand) would break.
   viscous-heating pattern          -> the Z (g - g_eq)/tau_bg source in S_b
   mirror / axis symmetry           -> upwind selection, index and axis mix-ups
   quadrature and limiter           -> Newton-Cotes weights, eq. VanLeer
+  single-slope reconstruction      -> conservation, second order, Sod (the option's own pins)
   paper-printed constants          -> gamma(K), c_v, Kn <-> mu_r, CFL
 """
 import json
@@ -167,11 +168,16 @@ def test_gresho_profile_is_balanced():
 # scheme invariants
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("dim,n,nv,Pr,Kn", [(1, 32, 24, 2.0 / 3.0, 1e-3), (1, 16, 17, 2.0, 10.0),
-                                            (2, 8, 10, 2.0 / 3.0, 1e-2), (2, 6, 9, 1.0, 1.0),
-                                            (3, 4, 6, 0.5, 1e-1)])
-def test_round_off_conservation_periodic(dim, n, nv, Pr, Kn):
+@pytest.mark.parametrize("dim,n,nv,Pr,Kn,recon", [(1, 32, 24, 2.0 / 3.0, 1e-3, "slopes_of_slopes"),
+                                                  (1, 16, 17, 2.0, 10.0, "slopes_of_slopes"),
+                                                  (2, 8, 10, 2.0 / 3.0, 1e-2, "slopes_of_slopes"),
+                                                  (2, 6, 9, 1.0, 1.0, "slopes_of_slopes"),
+                                                  (3, 4, 6, 0.5, 1e-1, "slopes_of_slopes"),
+                                                  (2, 8, 10, 2.0 / 3.0, 1e-2, "single_slope"),
+                                                  (3, 4, 6, 0.5, 1e-1, "single_slope")])
+def test_round_off_conservation_periodic(dim, n, nv, Pr, Kn, recon):
     prob = _periodic(dim, n, nv, seed=11 + dim, Kn=Kn, Pr=Pr)
+    prob["reconstruction"] = recon
     o = make_oracle(prob)
     t0 = _totals(o, prob)
     steps = 20
@@ -292,10 +298,12 @@ def test_mirror_symmetry_with_dirichlet_sides():
     assert abs(ra[0] - 1.0) > 1e-3  # the boundary states did act
 
 
-def test_sod_small_kn_matches_exact_riemann():
+@pytest.mark.parametrize("recon", ["slopes_of_slopes", "single_slope"])
+def test_sod_small_kn_matches_exact_riemann(recon):
     """Sec. 3.1 problem at the benchmark sizes (128 cells, 64 velocities,
-    gamma = 5/3, Kn = 1e-3, outflow, t = 0.2) against the exact Euler solution."""
-    p = wl.sod()
+    gamma = 5/3, Kn = 1e-3, outflow, t = 0.2) against the exact Euler solution
+    (both reconstructions)."""
+    p = wl.sod(reconstruction=recon)
     o = make_oracle(p)
     assert o.step(p["steps"]) == 0
     rho, u, T = o.moments()
@@ -361,12 +369,15 @@ def test_sod_prandtl_sweep_contact_conduction():
     assert grads[2] / grads[0] == pytest.approx(math.sqrt(2.25), rel=0.1)
 
 
-def test_free_streaming_second_order():
+@pytest.mark.parametrize("recon", ["slopes_of_slopes", "single_slope"])
+def test_free_streaming_second_order(recon):
     """tau = inf: every discrete velocity is advected on its own; the density
-    converges to sum_i w_i g0(x - xi_i t, xi_i) at second order."""
+    converges to sum_i w_i g0(x - xi_i t, xi_i) at second order (both
+    reconstructions)."""
     def err(n, nv=8, tend=0.25):
         prob = dict(dim=1, n=[n], lo=[0.0], hi=[1.0], bc=["periodic"], nv=[nv], vmin=[-3.0], vmax=[3.0],
-                    gamma=5.0 / 3.0, Pr=2.0 / 3.0, R=0.5, relax="tau", tau=math.inf, cfl=0.5)
+                    gamma=5.0 / 3.0, Pr=2.0 / 3.0, R=0.5, relax="tau", tau=math.inf, cfl=0.5,
+                    reconstruction=recon)
         x = (np.arange(n) + 0.5) / n
         prob["rho"] = 1.0 + 0.2 * np.sin(2 * np.pi * x)
         prob["u"] = np.zeros((1, n))
@@ -385,10 +396,12 @@ def test_free_streaming_second_order():
     assert min(orders) >= 1.8, (e, orders)
 
 
-def test_sound_wave_second_order_self_convergence():
+@pytest.mark.parametrize("recon", ["slopes_of_slopes", "single_slope"])
+def test_sound_wave_second_order_self_convergence(recon):
     def run(n, tend=0.2, eps=1e-3):
         prob = dict(dim=1, n=[n], lo=[0.0], hi=[1.0], bc=["periodic"], nv=[32], vmin=[-8.0], vmax=[8.0],
-                    gamma=5.0 / 3.0, Pr=2.0 / 3.0, R=0.5, relax="kn", Kn=1e-3, omega=0.5, T_ref=1.0, cfl=0.5)
+                    gamma=5.0 / 3.0, Pr=2.0 / 3.0, R=0.5, relax="kn", Kn=1e-3, omega=0.5, T_ref=1.0, cfl=0.5,
+                    reconstruction=recon)
         x = (np.arange(n) + 0.5) / n
         c = math.sqrt(5.0 / 3.0 * 0.5)
         prob["rho"] = 1.0 + eps * np.sin(2 * np.pi * x)
