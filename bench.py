@@ -253,6 +253,17 @@ def main():
         for st in ("f64", "f32"):
             sequential[st] = sequential_run(args.batched_problems, st)
 
+    # the single-slope reconstruction option (not the paper's), FP64, also
+    # before the headline legs
+    single_slope = None
+    if not args.no_fp32:
+        _, pss = workload(args.config, "f64")
+        pss["reconstruction"] = "single_slope"
+        N4, V4, wall4, ph4, _ = time_gpu(pss, args.steps, args.warmup)
+        single_slope = {"value": N4 * V4 * args.steps / wall4, "unit": "updates/s",
+                        "ms_per_step": 1e3 * wall4 / args.steps,
+                        "phase_ms": {k: float(v) for k, v in zip(PHASES, ph4)}}
+
     name, prob = workload(args.config, "f64")
     N, V, wall, phase_ms, io = time_gpu(prob, args.steps, args.warmup, args.copy_calibration)
     ups = N * V * args.steps / wall
@@ -270,6 +281,9 @@ def main():
                 "traffic_per_update": rec["traffic_bytes"] / (N * V) if rec else None,
                 "kernel_ms": float(phase_ms[dom]), "phase_ms": {k: float(v) for k, v in zip(PHASES, phase_ms)},
                 "algorithmic_bytes_per_update": kb,
+                # the measured HBM traffic of the kernel over its duration
+                "traffic_GBps": rec["traffic_bytes"] / (phase_ms[dom] * 1e-3) / 1e9 if rec else None,
+                "traffic_frac": rec["traffic_bytes"] / (phase_ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS if rec else None,
                 "step_algorithmic_frac": ALGO_BYTES["f64"] * ups / 1e9 / HBM_PEAK_GBS}
 
     out = {"metric": "phase-space updates/s", "value": ups, "unit": "updates/s", "n_gpus": 1,
@@ -299,6 +313,9 @@ def main():
                                       "speedup_vs_fp64": ups3 / ups, "speedup_vs_fp32": ups3 / ups32,
                                       "bf16_rows": io3["bf16_rows"], "rows": V3,
                                       "phase_ms": {k: float(v) for k, v in zip(PHASES, ph3)}}
+    if single_slope is not None:
+        single_slope["speedup_vs_fp64"] = single_slope["value"] / ups
+        out["single_slope_fp64"] = single_slope
     if args.batched_problems > 0:
         out["batched"] = batched_run(args.batched_problems, chunk=100)
         out["batched"]["speedup_vs_fp64_plain"] = out["batched"]["value"] / ups

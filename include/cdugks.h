@@ -79,6 +79,17 @@ enum { CDUGKS_QUAD_TRAPEZOID = 0, CDUGKS_QUAD_BOOLE = 1 };
  * reserves FP32 rows for it. */
 enum { CDUGKS_STORE_F64 = 0, CDUGKS_STORE_F32 = 1, CDUGKS_STORE_F32_BF16TAIL = 2 };
 
+/* Face reconstruction of the quarter-step field at t_{n+1/2} (Sec. 2.1,
+ * eq. relation).  SLOPES_OF_SLOPES is the paper's: the value at the face is
+ * phi_bar_plus(x_u) + delta sigma_d(u) from the upwind cell u, and the face
+ * gradient is itself reconstructed, sigma_f = sigma(u) + delta t_d(u) with t
+ * the Van Leer limited derivatives of the slopes along the face normal; the
+ * foot value is phi_bar_plus(x_f) - h xi . sigma_f.  SINGLE_SLOPE carries the
+ * upwind cell's limited slopes alone to the foot, phi_bar_plus(x_u) +
+ * (x_f - h xi - x_u) . sigma(u): the classic DUGKS form, D limited slopes
+ * per field and update instead of D + D^2. */
+enum { CDUGKS_RECON_SLOPES_OF_SLOPES = 0, CDUGKS_RECON_SINGLE_SLOPE = 1 };
+
 typedef struct {
     int dim;                /* D = 1, 2 or 3 */
     int64_t n[3];           /* cells per dimension (entries >= dim ignored) */
@@ -110,6 +121,7 @@ typedef struct {
     double dt;              /* <= 0: dt = cfl dx_min / (2 max_i |xi_i|) */
     int storage;            /* CDUGKS_STORE_* */
     int velocity_slices;    /* velocity-loop split across workgroups; 0 = auto */
+    int reconstruction;     /* CDUGKS_RECON_* */
 } cdugks_params;
 
 typedef struct cdugks_ctx cdugks_ctx;

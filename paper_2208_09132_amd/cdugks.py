@@ -26,6 +26,7 @@ BC = {"periodic": 0, "outflow": 1, "dirichlet": 2}
 RELAX = {"kn": 0, "mu": 1, "tau": 2}
 QUAD = {"trapezoid": 0, "boole": 1}
 STORE = {"f64": 0, "f32": 1, "f32_bf16tail": 2}
+RECON = {"slopes_of_slopes": 0, "single_slope": 1}
 
 ERROR_NAMES = {ERR_INVALID: "ERR_INVALID", ERR_NOMEM: "ERR_NOMEM", ERR_DEVICE: "ERR_DEVICE",
                ERR_NONPHYSICAL: "ERR_NONPHYSICAL", ERR_TOO_LARGE: "ERR_TOO_LARGE", ERR_BUSY: "ERR_BUSY",
@@ -54,7 +55,8 @@ class cdugks_params(ctypes.Structure):
                 ("omega", ctypes.c_double), ("relax_mode", ctypes.c_int), ("Kn", ctypes.c_double),
                 ("L_ref", ctypes.c_double), ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
                 ("mu_ref", ctypes.c_double), ("tau", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("dt", ctypes.c_double), ("storage", ctypes.c_int), ("velocity_slices", ctypes.c_int)]
+                ("dt", ctypes.c_double), ("storage", ctypes.c_int), ("velocity_slices", ctypes.c_int),
+                ("reconstruction", ctypes.c_int)]
 
 
 _lib = None
@@ -163,6 +165,7 @@ def describe(prob: dict):
     pa.cfl = float(prob.get("cfl", 0.5))
     pa.dt = float(prob.get("dt") or 0.0)
     pa.storage = STORE[prob.get("storage", "f64")]
+    pa.reconstruction = RECON[prob.get("reconstruction", "slopes_of_slopes")]
     pa.velocity_slices = int(prob.get("velocity_slices", 0))
     return sp, ve, pa
 

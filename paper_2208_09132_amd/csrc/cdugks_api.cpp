@@ -31,6 +31,14 @@ int hip_fail(hipError_t e, const char* what) {
 
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Bytes between consecutive velocity rows of a row of `bytes`: 256-byte
+// aligned, plus ROW_PAD for rows of 64 KB or more (a multiple of 8 and of 4,
+// so the pitch is a whole number of FP64 and FP32 elements).
+constexpr size_t ROW_PAD = 4352;
+static size_t row_pitch_bytes(size_t bytes) {
+    return align_up(bytes) + (bytes >= (size_t(1) << 16) ? ROW_PAD : 0);
+}
+
 // ---------------------------------------------------------------------------
 // problem set-up
 // ---------------------------------------------------------------------------
@@ -100,6 +108,9 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
         pa->storage != CDUGKS_STORE_F32_BF16TAIL)
         return fail(CDUGKS_ERR_INVALID, "unknown storage mode %d", pa->storage);
     r.storage = pa->storage;
+    if (pa->reconstruction != CDUGKS_RECON_SLOPES_OF_SLOPES && pa->reconstruction != CDUGKS_RECON_SINGLE_SLOPE)
+        return fail(CDUGKS_ERR_INVALID, "unknown reconstruction %d", pa->reconstruction);
+    r.recon = pa->reconstruction;
     r.gamma = pa->gamma;
     r.Pr = pa->Pr;
     r.R = pa->R;
@@ -208,12 +219,17 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
 
     // byte plan
     const size_t es = r.storage == CDUGKS_STORE_F64 ? 8 : 4;
-    const size_t NV = (size_t)r.N * r.V;
-    // a state array (g, b, quarter-step field): V rows of N values; the
-    // BF16-tail form starts every row on a 256-byte boundary and reserves an
-    // FP32 row for each (which rows hold BF16 is decided at init)
-    const size_t state_bytes =
-        r.storage == CDUGKS_STORE_F32_BF16TAIL ? (size_t)r.V * align_up((size_t)r.N * 4) : NV * es;
+    // a state array (g, b, quarter-step field): V rows of N values, r.pitch
+    // elements apart; the BF16-tail form starts every row on a 256-byte
+    // boundary and reserves an FP32 row for each (which rows hold BF16 is
+    // decided at init).  Rows of 64 KB or more are padded by ROW_PAD bytes:
+    // at power-of-two distances the same cells of consecutive velocity rows
+    // contend for the same memory channels (3-D FP32 face sums 48 -> 33 ms).
+    r.pitch = (long long)row_pitch_bytes((size_t)r.N * es) / (long long)es;
+    r.fv_pitch = (long long)row_pitch_bytes((size_t)r.NE * es) / (long long)es;
+    const size_t state_bytes = r.storage == CDUGKS_STORE_F32_BF16TAIL
+                                   ? (size_t)r.V * row_pitch_bytes((size_t)r.N * 4)
+                                   : (size_t)r.V * (size_t)r.pitch * es;
     // Consecutive regions are staggered by 4.25 KB each: arrays read at the
     // same element index (g, b, the quarter-step fields, the face values)
     // would otherwise sit at offsets that are multiples of a large power of
@@ -237,7 +253,7 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
     r.off_q[1] = quarter_stored(D) ? take(state_bytes) : 0;
     r.off_rows = r.storage == CDUGKS_STORE_F32_BF16TAIL ? take((size_t)r.V * 8) : 0;
     // face values: 2D blocks of V NE values, each block padded by the stagger
-    r.fv_stride = (long long)r.V * r.NE + (long long)(STAGGER / es);
+    r.fv_stride = (long long)r.V * r.fv_pitch + (long long)(STAGGER / es);
     r.off_FV = take((size_t)D * 2 * (size_t)r.fv_stride * es);
     r.off_FS = take((size_t)r.nslices * D * (2 * D + 3) * r.NE * 8);
     r.off_FP = take((size_t)D * NFP * r.NE * 8);
@@ -398,12 +414,15 @@ void fill_problem(const Resolved& r, char* base, Problem& P) {
     }
     P.FV = base + r.off_FV;
     P.fv_stride = r.fv_stride;
+    P.pitch = r.pitch;
+    P.fv_pitch = r.fv_pitch;
     P.dir_eq = r.any_dirichlet ? (const double*)(base + r.off_dir) : nullptr;
     P.FS = (double*)(base + r.off_FS);
     P.FP = (double*)(base + r.off_FP);
     P.G = (double*)(base + r.off_G);
     P.err = (int*)(base + r.off_err);
     P.rows = r.storage == CDUGKS_STORE_F32_BF16TAIL ? (const long long*)(base + r.off_rows) : nullptr;
+    P.recon = r.recon;
 }
 
 // Rows of the BF16-tail form: velocity i is a tail row when, for every
@@ -438,7 +457,7 @@ long long tail_rows(const Resolved& r, const std::vector<double>& vel, const dou
         }
         const bool tail = d2 > lim2;
         rows[i] = off | (tail ? 1 : 0);
-        off += (long long)align_up((size_t)r.N * (tail ? 2 : 4));
+        off += (long long)row_pitch_bytes((size_t)r.N * (tail ? 2 : 4));
         ntail += tail;
     }
     return ntail;
@@ -630,10 +649,10 @@ int cdugks_storage_info(cdugks_ctx* c, int64_t* bf16_rows, size_t* state_array_b
     if (state_array_bytes) {
         const Resolved& r = c->r;
         if (r.storage == CDUGKS_STORE_F32_BF16TAIL)
-            *state_array_bytes = (size_t)(r.V - c->bf16_rows) * align_up((size_t)r.N * 4) +
-                                 (size_t)c->bf16_rows * align_up((size_t)r.N * 2);
+            *state_array_bytes = (size_t)(r.V - c->bf16_rows) * row_pitch_bytes((size_t)r.N * 4) +
+                                 (size_t)c->bf16_rows * row_pitch_bytes((size_t)r.N * 2);
         else
-            *state_array_bytes = (size_t)r.N * r.V * (r.storage == CDUGKS_STORE_F64 ? 8 : 4);
+            *state_array_bytes = (size_t)r.V * (size_t)r.pitch * (r.storage == CDUGKS_STORE_F64 ? 8 : 4);
     }
     return CDUGKS_OK;
 }

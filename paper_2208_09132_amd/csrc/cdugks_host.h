@@ -20,6 +20,7 @@ struct Resolved {
     double vmin[3], vmax[3];
     int quad;
     int storage;
+    int recon;  // CDUGKS_RECON_*
     int nslices, nslices_upd;
     int relax;
     double dt, gamma, Pr, R, omega, K, c_int, mu_ref, T_ref, tau_inv;
@@ -29,6 +30,7 @@ struct Resolved {
     size_t off_rows;      // BF16-tail form: row words [V]
     size_t bytes;
     long long fv_stride;  // elements between the (d, field) blocks of the face values
+    long long pitch, fv_pitch;  // elements between velocity rows (state arrays, face values)
     double dir[3][2][5];  // Dirichlet states (rho, u_x, u_y, u_z, T) per dimension and side
     bool any_dirichlet;
 };

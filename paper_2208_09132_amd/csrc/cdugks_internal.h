@@ -65,10 +65,12 @@ struct Problem {
     const void* g_in; const void* b_in; void* g_out; void* b_out;
     const double* W_in; double* W_out;
     const double* P_in; double* P_out;
-    void* qg;     // quarter-step fields [V][N] for g and b, storage precision
+    void* qg;     // quarter-step fields [V][pitch] for g and b, storage precision
     void* qb;     // (null unless quarter_stored(D))
-    void* FV;     // face values phi_bar [D][2][fv_stride], block (d, field) holds [V][NE]
-    long long fv_stride;  // >= V NE (padded so the blocks do not alias)
+    void* FV;     // face values phi_bar [D][2][fv_stride], block (d, field) holds [V][fv_pitch]
+    long long fv_stride;  // >= V fv_pitch (padded so the blocks do not alias)
+    long long pitch;      // elements between velocity rows of g, b and the quarter-step fields (>= N)
+    long long fv_pitch;   // elements between velocity rows of a face-value block (>= NE)
     double* FS;   // face partial sums [nslices][D][2D+3][NE]
     double* FP;   // face coefficients [D][NFP][NE]
     double* G;    // flux moments [D][D+2][NE]
@@ -78,6 +80,7 @@ struct Problem {
     // inside the state arrays g, b and the quarter-step fields, bit 0 set for
     // a BF16 row; null otherwise
     const long long* rows;
+    int recon;    // 0: slopes of slopes (Sec. 2.1), 1: single slope
 };
 
 // One workgroup's assignment in a batched launch.
@@ -100,15 +103,17 @@ hipError_t launch_moments(const Problem& P, const double* W, double* rho, double
                           hipStream_t s);
 hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStream_t s);
 
-// Batched: one launch per phase across problems of one class (storage, and
-// whether they have Dirichlet sides, which selects the face-sum variant).  The
+// Batched: one launch per phase across problems of one class (storage,
+// whether they have Dirichlet sides, and the reconstruction option, which
+// select the face-sum variant).  The
 // tile-kernel launches are persistent (grid = resident slots; workgroups take
 // items from the device counter `queue`, which must be 0 at launch, and reset
 // the counter `other` of the other kernel of the pair); maxd is the largest
 // dimension in the class.  The per-face and per-cell closures take
 // per-problem prefix offsets (in threads).
 hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int grid,
-                                    int maxd, int storage, bool dirichlet, int* queue, int* other, hipStream_t s);
+                                    int maxd, int storage, bool dirichlet, bool single_slope, int* queue,
+                                    int* other, hipStream_t s);
 hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, int nitems, int grid, int maxd,
                                  int storage, int* queue, int* other, hipStream_t s);
 int batched_blocks_per_cu(int maxd, int storage, bool update);

@@ -1,7 +1,9 @@
 // HIP kernels of one CDUGKS time step for gfx950.
 //
 // Data layout (per problem):
-//   g, b        [V][N]  velocity-major, cells fastest (x fastest); FP64 or FP32
+//   g, b        [V][pitch]  velocity-major, cells fastest (x fastest); FP64 or
+//               FP32; rows of pitch >= N elements (padded so that large rows
+//               do not sit at power-of-two distances)
 //   W           [D+2][N] FP64 conserved variables (rho, rho u, rho E)
 //   cell coefs  [NPC][N] FP64, derived from W (see cdugks_internal.h)
 //   face sums   [slices][D][2D+3][NE], face coefs [D][NFP][NE], flux [D][D+2][NE]
@@ -138,7 +140,7 @@ __device__ __forceinline__ typename StoreT<ST>::R state_load(const Problem& P, c
         if (o & 1) return (unsigned)((const unsigned short*)row)[c];
         return ((const unsigned*)row)[c];
     } else {
-        return ((const ST*)base)[(long long)i * P.N + c];
+        return ((const ST*)base)[(long long)i * P.pitch + c];
     }
 }
 template <typename ST>
@@ -178,8 +180,8 @@ __device__ __forceinline__ void state_st(const Problem& P, void* base, int i, lo
             else ((float*)row)[c] = f;
         }
     } else {
-        if constexpr (STREAM) st_stream<ST>(base, (long long)i * P.N + c, v);
-        else st<ST>(base, (long long)i * P.N + c, v);
+        if constexpr (STREAM) st_stream<ST>(base, (long long)i * P.pitch + c, v);
+        else st<ST>(base, (long long)i * P.pitch + c, v);
     }
 }
 
@@ -207,7 +209,7 @@ __device__ __forceinline__ void load_slots(const Problem& P, const void* sg, con
             }
         }
     } else {
-        const long long vb = (long long)i * P.N;
+        const long long vb = (long long)i * P.pitch;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             og[k] = ((const ST*)sg)[vb + src[k]];
@@ -507,6 +509,16 @@ __device__ __forceinline__ CT face_value_at(CT qU, const CT* haU, const CT* haL,
     return val;
 }
 
+// The single-slope option: the upwind cell's own slopes carried to the foot,
+// v = q(u) + s ha_d - sum_e lam2_e ha_e (no slopes of slopes).
+template <int D, typename CT>
+__device__ __forceinline__ CT face_value_single(CT qU, const CT* haU, int d, CT s, const Vel& v) {
+    CT val = qU + s * haU[d];
+#pragma unroll
+    for (int e = 0; e < D; ++e) val -= CT(v.lam2[e]) * haU[e];
+    return val;
+}
+
 // Face coefficients used to invert eq. phibar at a face: NFC per face.
 template <int D>
 struct FaceCoef {
@@ -615,7 +627,9 @@ struct GaussWalk {
 // DIR: the problem has Dirichlet sides; their ghost slots of the q box take
 // the fixed states' equilibria (a separate instantiation keeps the register
 // budget of the others unchanged).
-template <int D, typename ST, bool DIR = false>
+// SS: the single-slope reconstruction option (stage 3 reads only the upwind
+// cell's slopes).
+template <int D, typename ST, bool DIR = false, bool SS = false>
 struct FaceSumKernel {
     using G = Geo<D>;
     // stencil arithmetic (quarter-step values in LDS, limiters, face values) in
@@ -939,29 +953,39 @@ struct FaceSumKernel {
                     const CT* sa = f == 0 ? sa0 : sa1;
                     CT aU[D], aL[D], aR[D];
                     CT left = 0, right = 0;
-                    if (xd >= 0.0) {  // upwind c - d: its left and right neighbours are c - 2d and c
+                    if constexpr (SS) {
+                        if (xd >= 0.0) {  // upwind c - d
 #pragma unroll
-                        for (int e = 0; e < D; ++e) {
-                            aU[e] = sa[e * G::NA + a_m];
-                            aL[e] = sa[e * G::NA + a_mm];
-                            aR[e] = a_own[f][e];
+                            for (int e = 0; e < D; ++e) aU[e] = sa[e * G::NA + a_m];
+                            left = face_value_single<D, CT>(sq[q_m], aU, d, CT(1), v);
                         }
-                        left = face_value_at<D, CT>(sq[q_m], aU, aL, aR, d, CT(1), v);
-                    }
-                    if (xd <= 0.0) {  // upwind c: neighbours c - d and c + d
+                        if (xd <= 0.0)  // upwind c
+                            right = face_value_single<D, CT>(q_own[f], a_own[f], d, CT(-1), v);
+                    } else {
+                        if (xd >= 0.0) {  // upwind c - d: its left and right neighbours are c - 2d and c
 #pragma unroll
-                        for (int e = 0; e < D; ++e) {
-                            aU[e] = a_own[f][e];
-                            aL[e] = sa[e * G::NA + a_m];
-                            aR[e] = sa[e * G::NA + a_p];
+                            for (int e = 0; e < D; ++e) {
+                                aU[e] = sa[e * G::NA + a_m];
+                                aL[e] = sa[e * G::NA + a_mm];
+                                aR[e] = a_own[f][e];
+                            }
+                            left = face_value_at<D, CT>(sq[q_m], aU, aL, aR, d, CT(1), v);
                         }
-                        right = face_value_at<D, CT>(q_own[f], aU, aL, aR, d, CT(-1), v);
+                        if (xd <= 0.0) {  // upwind c: neighbours c - d and c + d
+#pragma unroll
+                            for (int e = 0; e < D; ++e) {
+                                aU[e] = a_own[f][e];
+                                aL[e] = sa[e * G::NA + a_m];
+                                aR[e] = sa[e * G::NA + a_p];
+                            }
+                            right = face_value_at<D, CT>(q_own[f], aU, aL, aR, d, CT(-1), v);
+                        }
                     }
                     fv[f] = xd > 0.0 ? left : (xd < 0.0 ? right : CT(0.5) * (left + right));
                 }
                 const double vg = fv[0], vb2 = fv[1];
                 if (fvalid[d]) {
-                    const long long o = (long long)(2 * d) * fstride + (long long)i * NE + fe;
+                    const long long o = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch + fe;
                     st_stream<CT>(P.FV, o, vg);
                     st_stream<CT>(P.FV, o + fstride, vb2);
                 }
@@ -1116,13 +1140,13 @@ struct UpdateKernel {
                         }
                     }
                 }
-                const long long vb = (long long)i * N;
+                const long long vb = (long long)i * P.pitch;
                 const double g = ld<ST>(P.g_in, vb + cc);
                 const double b = ld<ST>(P.b_in, vb + cc);
                 double Fg = 0.0, Fb = 0.0;
     #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    const long long o = (long long)(2 * d) * fstride + (long long)i * NE;
+                    const long long o = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch;
                     const double eql = WALKER ? wl[d].template value<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v)
                                               : maxwellian<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v);
                     const double eqr = WALKER ? wr[d].template value<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v)
@@ -1182,7 +1206,7 @@ struct UpdateKernel {
                 double Fg = 0.0, Fb = 0.0;
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    const long long fo = (long long)(2 * d) * fstride + (long long)i * NE;
+                    const long long fo = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch;
                     const double eql = maxwellian<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v);
                     const double eqr = maxwellian<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v);
                     double gl, bl, gr, br;
@@ -1231,9 +1255,9 @@ struct UpdateKernel {
 template <int D>
 constexpr int face_sum_waves() { return D == 1 ? 4 : (D == 2 ? 3 : 1); }
 
-template <int D, typename ST, bool DIR>
+template <int D, typename ST, bool DIR, bool SS>
 __global__ __launch_bounds__(WG, face_sum_waves<D>()) void k_face_sums(Problem P) {
-    using K = FaceSumKernel<D, ST, DIR>;
+    using K = FaceSumKernel<D, ST, DIR, SS>;
     __shared__ typename K::Smem sm;
     int ntiles = P.tiles1[0] * P.tiles1[1] * P.tiles1[2];
     int q = xcd_remap(blockIdx.x, gridDim.x);
@@ -1276,24 +1300,24 @@ __device__ __forceinline__ T load_uniform(const T* p) {
     return r;
 }
 
-template <typename ST, int MAXD, bool DIR>
+template <typename ST, int MAXD, bool DIR, bool SS>
 __global__ __launch_bounds__(WG) void k_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems,
                                                           int* queue, int* other) {
     __shared__ union U {
-        typename FaceSumKernel<1, ST, DIR>::Smem s1;
-        typename FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR>::Smem s2;
-        typename FaceSumKernel<MAXD >= 3 ? 3 : 1, ST, DIR>::Smem s3;
+        typename FaceSumKernel<1, ST, DIR, SS>::Smem s1;
+        typename FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR, SS>::Smem s2;
+        typename FaceSumKernel<MAXD >= 3 ? 3 : 1, ST, DIR, SS>::Smem s3;
     } sm;
     __shared__ int slot;
     if (blockIdx.x == 0 && threadIdx.x == 0) *other = 0;
     for (int w = next_item(queue, &slot); w < nitems; w = next_item(queue, &slot)) {
         const WorkItem it = load_uniform(items + w);
         const Problem P = load_uniform(probs + it.prob);
-        if (P.D == 1) FaceSumKernel<1, ST, DIR>::run(P, it.tile, it.slice, P.nslices, sm.s1);
+        if (P.D == 1) FaceSumKernel<1, ST, DIR, SS>::run(P, it.tile, it.slice, P.nslices, sm.s1);
         else if (MAXD >= 2 && P.D == 2)
-            FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR>::run(P, it.tile, it.slice, P.nslices, sm.s2);
+            FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR, SS>::run(P, it.tile, it.slice, P.nslices, sm.s2);
         else if (MAXD >= 3)
-            FaceSumKernel<MAXD >= 3 ? 3 : 1, ST, DIR>::run(P, it.tile, it.slice, P.nslices, sm.s3);
+            FaceSumKernel<MAXD >= 3 ? 3 : 1, ST, DIR, SS>::run(P, it.tile, it.slice, P.nslices, sm.s3);
     }
 }
 
@@ -1569,14 +1593,26 @@ hipError_t launch_init(const Problem& P, const double* rho, const double* u, con
 
 hipError_t launch_face_sums(const Problem& P, hipStream_t s) {
     unsigned nb = (unsigned)(P.tiles1[0] * P.tiles1[1] * P.tiles1[2] * P.nslices);
-    if (P.dir_eq) {
-#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT, true>), dim3(nb), dim3(WG), 0, s, P)
-        CDG_DISPATCH(P.storage, P.D, CDG_L);
+    if (P.recon == 0) {
+        if (P.dir_eq) {
+#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT, true, false>), dim3(nb), dim3(WG), 0, s, P)
+            CDG_DISPATCH(P.storage, P.D, CDG_L);
 #undef CDG_L
+        } else {
+#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT, false, false>), dim3(nb), dim3(WG), 0, s, P)
+            CDG_DISPATCH(P.storage, P.D, CDG_L);
+#undef CDG_L
+        }
     } else {
-#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT, false>), dim3(nb), dim3(WG), 0, s, P)
-        CDG_DISPATCH(P.storage, P.D, CDG_L);
+        if (P.dir_eq) {
+#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT, true, true>), dim3(nb), dim3(WG), 0, s, P)
+            CDG_DISPATCH(P.storage, P.D, CDG_L);
 #undef CDG_L
+        } else {
+#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT, false, true>), dim3(nb), dim3(WG), 0, s, P)
+            CDG_DISPATCH(P.storage, P.D, CDG_L);
+#undef CDG_L
+        }
     }
     return hipGetLastError();
 }
@@ -1597,7 +1633,7 @@ int tile_blocks_per_cu(int D, int storage, bool update) {
         CDG_DISPATCH(storage, D, CDG_L);
 #undef CDG_L
     } else {
-#define CDG_L(DD, TT) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums<DD, TT, false>), WG, 0)
+#define CDG_L(DD, TT) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums<DD, TT, false, false>), WG, 0)
         CDG_DISPATCH(storage, D, CDG_L);
 #undef CDG_L
     }
@@ -1650,21 +1686,39 @@ hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStre
     } while (0)
 
 hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int grid,
-                                    int maxd, int storage, bool dirichlet, int* queue, int* other, hipStream_t s) {
+                                    int maxd, int storage, bool dirichlet, bool single_slope, int* queue,
+                                    int* other, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
+#define CDG_B(DIRV, SSV)                                                                                     \
+    do {                                                                                                     \
+        if ((STORAGE_) == 0) {                                                                               \
+            if (maxd == 1) CDG_LB(double, 1, DIRV, SSV);                                                     \
+            else if (maxd == 2) CDG_LB(double, 2, DIRV, SSV);                                                \
+            else CDG_LB(double, 3, DIRV, SSV);                                                               \
+        } else if ((STORAGE_) == 1) {                                                                        \
+            if (maxd == 1) CDG_LB(float, 1, DIRV, SSV);                                                      \
+            else if (maxd == 2) CDG_LB(float, 2, DIRV, SSV);                                                 \
+            else CDG_LB(float, 3, DIRV, SSV);                                                                \
+        } else {                                                                                             \
+            if (maxd == 1) CDG_LB(Bf16Tail, 1, DIRV, SSV);                                                   \
+            else if (maxd == 2) CDG_LB(Bf16Tail, 2, DIRV, SSV);                                              \
+            else CDG_LB(Bf16Tail, 3, DIRV, SSV);                                                             \
+        }                                                                                                    \
+    } while (0)
+#define CDG_LB(TT, MD, DIRV, SSV)                                                                            \
+    hipLaunchKernelGGL((k_face_sums_batched<TT, MD, DIRV, SSV>), dim3(grid), dim3(WG), 0, s, probs, items,  \
+                       nitems, queue, other)
+#define STORAGE_ storage
     if (dirichlet) {
-#define CDG_L(TT, MD)                                                                                   \
-    hipLaunchKernelGGL((k_face_sums_batched<TT, MD, true>), dim3(grid), dim3(WG), 0, s, probs, items, nitems, \
-                       queue, other)
-        CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
-#undef CDG_L
+        if (single_slope) CDG_B(true, true);
+        else CDG_B(true, false);
     } else {
-#define CDG_L(TT, MD)                                                                                    \
-    hipLaunchKernelGGL((k_face_sums_batched<TT, MD, false>), dim3(grid), dim3(WG), 0, s, probs, items, nitems, \
-                       queue, other)
-        CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
-#undef CDG_L
+        if (single_slope) CDG_B(false, true);
+        else CDG_B(false, false);
     }
+#undef STORAGE_
+#undef CDG_LB
+#undef CDG_B
     return hipGetLastError();
 }
 
@@ -1687,7 +1741,7 @@ int batched_blocks_per_cu(int maxd, int storage, bool update) {
         CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
 #undef CDG_L
     } else {
-#define CDG_L(TT, MD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums_batched<TT, MD, false>), WG, 0)
+#define CDG_L(TT, MD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums_batched<TT, MD, false, false>), WG, 0)
         CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
 #undef CDG_L
     }

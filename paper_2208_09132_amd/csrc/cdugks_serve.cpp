@@ -37,6 +37,7 @@ namespace {
 struct StorageClass {
     int storage = 0;
     bool dirichlet = false;  // members have Dirichlet sides (face-sum variant)
+    bool single_slope = false;  // members use the single-slope reconstruction
     int maxd = 1;
     WorkItem* items_fs = nullptr;  // device
     int n_fs = 0, grid_fs = 0;
@@ -77,7 +78,7 @@ std::string class_key(const Resolved& r) {
     long long nb = 1;
     while (nb < r.N) nb <<= 1;  // cell-count bucket: next power of two
     char buf[128];
-    snprintf(buf, sizeof buf, "d%d_s%d_v%lld_n%lld", r.D, r.storage, r.V, nb);
+    snprintf(buf, sizeof buf, "d%d_s%d_r%d_v%lld_n%lld", r.D, r.storage, r.recon, r.V, nb);
     return buf;
 }
 
@@ -141,7 +142,8 @@ hipError_t enqueue_batch_step(cdugks_batch* b, int phase) {
     const int np = (int)b->ctxs.size();
     const Problem* probs = b->d_probs[phase];
     for (auto& c : b->classes)
-        if ((e = launch_face_sums_batched(probs, c.items_fs, c.n_fs, c.grid_fs, c.maxd, c.storage, c.dirichlet, c.queue,
+        if ((e = launch_face_sums_batched(probs, c.items_fs, c.n_fs, c.grid_fs, c.maxd, c.storage, c.dirichlet,
+                                            c.single_slope, c.queue,
                                           c.queue + 1, b->stream)) !=
             hipSuccess)
             return e;
@@ -231,11 +233,12 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
     b->cell_total = ct;
     // work lists per class (index 2 storage + Dirichlet), sorted by estimated
     // cost (largest first)
-    constexpr int NCLASS = 6;  // 3 storage forms x (with, without Dirichlet sides)
+    // 3 storage forms x (with, without Dirichlet sides) x 2 reconstructions
+    constexpr int NCLASS = 12;
     std::vector<std::vector<WorkItem>> fs(NCLASS), up(NCLASS);
     std::vector<std::vector<double>> cfs(NCLASS), cup(NCLASS);
-    int maxd[NCLASS] = {0, 0, 0, 0, 0, 0};
-    auto class_of = [](const Resolved& r) { return 2 * r.storage + (r.any_dirichlet ? 1 : 0); };
+    int maxd[NCLASS] = {};
+    auto class_of = [](const Resolved& r) { return (2 * r.storage + (r.any_dirichlet ? 1 : 0)) * 2 + r.recon; };
     for (int j = 0; j < count; ++j) {
         const Resolved& r = ctxs[j]->r;
         const int s = class_of(r);
@@ -307,8 +310,9 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
     for (int s = 0; s < NCLASS; ++s) {
         if (fs[s].empty()) continue;
         StorageClass sc;
-        sc.storage = s / 2;
-        sc.dirichlet = s % 2 == 1;
+        sc.storage = s / 4;
+        sc.dirichlet = (s / 2) % 2 == 1;
+        sc.single_slope = s % 2 == 1;
         sc.maxd = maxd[s];
         // persistent grids: resident slots (times the tuned factor of the
         // largest class member), never more than the work items

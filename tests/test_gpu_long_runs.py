@@ -1,0 +1,71 @@
+"""GPU parity at the benchmark workloads' full sizes over their long runs,
+against oracle moments stored by tests/golden/make_oracle_references.py
+(which calls only the oracle): the Kelvin-Helmholtz layer (256^2 x 28^2) in
+FP64 after 50 steps and in FP32 and FP64 after its 2000 steps, and the 3-D
+shear's 16^3-velocity grid on 16^3 cells in FP32 after its 500 steps at
+Kn 1e-3, 1e-1 and 10.  Each run uses the single-problem launch
+configuration the benchmark times; moments are compared at a seeded sample
+of cells (all cells in 3-D)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2208_09132_amd import cdugks as cd
+from paper_2208_09132_amd import workloads as wl
+from tests.helpers import moment_errors
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _ref(name):
+    path = os.path.join(GOLDEN, f"oracle_{name}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not written yet (tests/golden/make_oracle_references.py)")
+    ref = np.load(path)
+    if not bool(ref["complete"]):
+        pytest.skip(f"{path} holds a partial run")
+    return ref
+
+
+def _check(prob, ref, checkpoints, tol):
+    idx = ref["cells"]
+    s = cd.Solver(prob)
+    assert abs(s.dt - float(ref["dt"])) <= 1e-15 * float(ref["dt"])
+    done, errs = 0, {}
+    for k in checkpoints:
+        s.step(k - done)
+        done = k
+        rho, u, T = s.moments()
+        got = (rho[idx], u[:, idx], T[idx])
+        want = (ref[f"rho_{k}"], ref[f"u_{k}"], ref[f"T_{k}"])
+        errs[k] = moment_errors(want, got, prob.get("gamma", 5.0 / 3.0), prob.get("R", 0.5))
+        _log(f"  {prob['dim']}D storage={prob.get('storage')} steps={k}: errors rho/u/T = {errs[k]}")
+        assert max(errs[k]) <= tol[k], (k, errs[k])
+    s.close()
+    return errs
+
+
+def test_kelvin_helmholtz_fp64_50_steps():
+    _check(wl.kelvin_helmholtz(), _ref("kh2d_256_v28"), [50], {50: 1e-12})
+
+
+def test_kelvin_helmholtz_fp32_2000_steps():
+    _check(wl.kelvin_helmholtz(storage="f32"), _ref("kh2d_256_v28"), [50, 2000], {50: 1e-5, 2000: 1e-5})
+
+
+def test_kelvin_helmholtz_fp64_2000_steps():
+    _check(wl.kelvin_helmholtz(), _ref("kh2d_256_v28"), [2000], {2000: 1e-12})
+
+
+@pytest.mark.parametrize("kn,tag", [(1e-3, "kn1e-3"), (1e-1, "kn1e-1"), (10.0, "kn10")])
+def test_shear3d_velocity_grid_fp32_500_steps(kn, tag):
+    _check(wl.shear3d(n=16, nv=16, Kn=kn), _ref(f"shear3d_16_v16_{tag}"), [500], {500: 1e-5})
