@@ -12,7 +12,7 @@ cells when there are at most 4096), the cell indices, the time step and the
 step counts.  The GPU tests run the same workloads in the benchmark's launch
 configuration and compare at those cells.
 
-    python tests/golden/make_oracle_references.py [kh] [shear3d]
+    python tests/golden/make_oracle_references.py [kh] [shear3d | shear3d:kn1e-3 ...] [--out DIR]
 """
 import math
 import os
@@ -39,33 +39,45 @@ def _sample(N: int, seed: int) -> np.ndarray:
     return np.sort(np.random.default_rng(seed).choice(N, SAMPLE, replace=False))
 
 
-def run(name: str, prob: dict, checkpoints, seed: int) -> None:
+def run(name: str, prob: dict, checkpoints, seed: int, outdir: str = HERE) -> None:
     dt = oracle_dt(prob)
     o = make_oracle(prob, dt=dt)
     idx = _sample(o.N, seed)
     out = {"cells": idx, "dt": np.float64(dt), "checkpoints": np.array(checkpoints, dtype=np.int64)}
     done, t0 = 0, time.time()
     for k in checkpoints:
-        assert o.step(k - done) == 0
-        done = k
+        while done < k:  # progress every 50 steps
+            n = min(50, k - done)
+            assert o.step(n) == 0
+            done += n
+            print(f"{name}: step {done} after {time.time() - t0:.0f} s", flush=True)
         rho, u, T = o.moments()
         out[f"rho_{k}"] = rho[idx]
         out[f"u_{k}"] = u[:, idx]
         out[f"T_{k}"] = T[idx]
         print(f"{name}: {k} steps after {time.time() - t0:.0f} s", flush=True)
         # partial file after each checkpoint (a long run can be resumed from scratch only)
-        np.savez_compressed(os.path.join(HERE, f"oracle_{name}.npz"), **out,
+        np.savez_compressed(os.path.join(outdir, f"oracle_{name}.npz"), **out,
                             complete=np.array(k == checkpoints[-1]))
 
 
-def main(which):
+SHEAR3D = {"kn1e-3": 1e-3, "kn1e-1": 1e-1, "kn10": 10.0}
+
+
+def main(which, outdir=HERE):
     orc.build(force=False)
     if "kh" in which:
-        run("kh2d_256_v28", wl.kelvin_helmholtz(), [50, 1000, 2000], seed=1)
-    if "shear3d" in which:
-        for kn, tag in ((1e-3, "kn1e-3"), (1e-1, "kn1e-1"), (10.0, "kn10")):
-            run(f"shear3d_16_v16_{tag}", wl.shear3d(n=16, nv=16, Kn=kn), [500], seed=2)
+        run("kh2d_256_v28", wl.kelvin_helmholtz(), [50, 1000, 2000], seed=1, outdir=outdir)
+    for tag, kn in SHEAR3D.items():
+        if "shear3d" in which or f"shear3d:{tag}" in which:
+            run(f"shear3d_16_v16_{tag}", wl.shear3d(n=16, nv=16, Kn=kn), [500], seed=2, outdir=outdir)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["kh", "shear3d"])
+    args = sys.argv[1:]
+    outdir = HERE
+    if "--out" in args:
+        k = args.index("--out")
+        outdir = args[k + 1]
+        del args[k:k + 2]
+    main(args or ["kh", "shear3d"], outdir)
