@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
-Two kinds of summary, both markdown with a machine-readable JSON block:
+Three kinds of summary, all markdown with a machine-readable JSON block:
 
 * ``trace``: the ``*_kernel_stats.csv`` of a ``--kernel-trace --stats`` run,
   one row per kernel (calls, average, min, max duration).
@@ -9,6 +9,8 @@ Two kinds of summary, both markdown with a machine-readable JSON block:
   reads for a plain copy kernel of known size in the same run: the library's
   FP64-to-FP64 distribution copy (``k_to_f64<double>``, n doubles read and n
   written per dispatch).
+* ``counters``: per-dispatch means of SQ counters of one kernel, with the
+  instruction counters also per update.
 
 The JSON block records a digest of the library's kernel and launch sources
 (:func:`source_digest`); the benchmark only reports traffic from a summary
@@ -16,6 +18,7 @@ whose digest matches the sources it runs.
 
     python -m paper_2208_09132_amd.profiling trace <csv_dir> <out.md> --title T --command C
     python -m paper_2208_09132_amd.profiling pmc <fetch_dir> <write_dir> <out.md> --kernel K ...
+    python -m paper_2208_09132_amd.profiling counters <csv_dir> <out.md> --kernel K --counter C ...
 """
 from __future__ import annotations
 
@@ -144,6 +147,32 @@ def write_pmc(fetch_dir, write_dir, out, kernel, title, commands, units_per_laun
         f.write("\n".join(lines))
 
 
+def write_counters(csv_dir, out, kernel, counters, title, command, units_per_launch, wave_size=64):
+    """Per-dispatch means of SQ counters for one kernel, and per update
+    (units) where the counter counts wave instructions: instructions per
+    update = counter / (units / wave size)."""
+    means = {c: counter_means(csv_dir, c) for c in counters}
+    name = _find(means[counters[0]], kernel)
+    vals = {c: means[c][_find(means[c], kernel)] for c in counters}
+    waves_per_launch = units_per_launch / wave_size
+    rec = {"digest": source_digest(), "kernel": name, "units_per_launch": units_per_launch,
+           "per_dispatch": vals,
+           "per_update": {c: v / waves_per_launch for c, v in vals.items() if c.startswith("SQ_INSTS")}}
+    if "SQ_ACTIVE_INST_VALU" in vals and "SQ_WAVE_CYCLES" in vals and vals["SQ_WAVE_CYCLES"] > 0:
+        rec["valu_active_per_wave_cycle"] = vals["SQ_ACTIVE_INST_VALU"] / vals["SQ_WAVE_CYCLES"]
+    lines = [f"# SQ counters: {title}", "", "Command (from the repository root; committed files only):", "",
+             "    " + command, "", f"Library sources digest: `{source_digest()}`.", "",
+             "| counter | per dispatch | per update (instruction counters) |", "|---|---|---|"]
+    for c, v in vals.items():
+        pu = rec["per_update"].get(c)
+        lines.append(f"| {c} | {v:.4g} | {'' if pu is None else f'{pu:.1f}'} |")
+    if "valu_active_per_wave_cycle" in rec:
+        lines += ["", f"SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES = {rec['valu_active_per_wave_cycle']:.3f}."]
+    lines += ["", "```json", json.dumps(rec, indent=1), "```", ""]
+    with open(out, "w") as f:
+        f.write("\n".join(lines))
+
+
 def load_record(md_path: str):
     """The JSON block of a summary, or None."""
     try:
@@ -175,7 +204,18 @@ def main():
     p.add_argument("--units", type=float, required=True, help="updates per launch")
     p.add_argument("--algo-bytes", type=float, required=True, help="algorithmic bytes per update")
     p.add_argument("--copy-bytes", type=float, required=True, help="bytes read (and written) per copy dispatch")
+    c = sub.add_parser("counters")
+    c.add_argument("csv_dir")
+    c.add_argument("out")
+    c.add_argument("--kernel", required=True, help="regex selecting one kernel name")
+    c.add_argument("--counter", action="append", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", required=True)
+    c.add_argument("--units", type=float, required=True, help="updates per launch")
     a = ap.parse_args()
+    if a.mode == "counters":
+        write_counters(a.csv_dir, a.out, a.kernel, a.counter, a.title, a.command, a.units)
+        return
     if a.mode == "trace":
         write_trace(a.csv_dir, a.out, a.title, a.command, a.note, a.tail_kernel, a.tail)
     else:
