@@ -85,6 +85,10 @@ def time_gpu(prob, steps: int, warmup: int, copy_calibration: bool = False):
         # each): a plain copy of known size for calibrating HBM counters
         s.distributions()
     s.close()
+    # hand the arena back to the device, so that the next leg gets a fresh
+    # allocation rather than a piece of this one's cached block (the 3-D FP32
+    # face sums ran 1.9x slower in the reused block)
+    torch.cuda.empty_cache()
     return N, V, wall, phase_ms, {"init_s": t_init, "moments_readback_s": t_read, "bf16_rows": bf16_rows}
 
 

@@ -35,8 +35,9 @@ static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // aligned, plus ROW_PAD for rows of 64 KB or more (a multiple of 8 and of 4,
 // so the pitch is a whole number of FP64 and FP32 elements).
 constexpr size_t ROW_PAD = 4352;
-static size_t row_pitch_bytes(size_t bytes) {
-    return align_up(bytes) + (bytes >= (size_t(1) << 16) ? ROW_PAD : 0);
+constexpr size_t FV_ROW_PAD = 4352;
+static size_t row_pitch_bytes(size_t bytes, size_t pad = ROW_PAD) {
+    return align_up(bytes) + (bytes >= (size_t(1) << 16) ? pad : 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -226,7 +227,7 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
     // at power-of-two distances the same cells of consecutive velocity rows
     // contend for the same memory channels (3-D FP32 face sums 48 -> 33 ms).
     r.pitch = (long long)row_pitch_bytes((size_t)r.N * es) / (long long)es;
-    r.fv_pitch = (long long)row_pitch_bytes((size_t)r.NE * es) / (long long)es;
+    r.fv_pitch = (long long)row_pitch_bytes((size_t)r.NE * es, FV_ROW_PAD) / (long long)es;
     const size_t state_bytes = r.storage == CDUGKS_STORE_F32_BF16TAIL
                                    ? (size_t)r.V * row_pitch_bytes((size_t)r.N * 4)
                                    : (size_t)r.V * (size_t)r.pitch * es;

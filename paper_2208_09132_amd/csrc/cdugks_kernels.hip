@@ -209,11 +209,15 @@ __device__ __forceinline__ void load_slots(const Problem& P, const void* sg, con
             }
         }
     } else {
-        const long long vb = (long long)i * P.pitch;
+        // the row's base address is uniform (scalar) and the cell offsets
+        // are loop-invariant, so each load is a scalar base plus a fixed
+        // vector offset
+        const ST* const rg = (const ST*)sg + (long long)i * P.pitch;
+        const ST* const rb = (const ST*)sb + (long long)i * P.pitch;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            og[k] = ((const ST*)sg)[vb + src[k]];
-            ob[k] = ((const ST*)sb)[vb + src[k]];
+            og[k] = rg[src[k]];
+            ob[k] = rb[src[k]];
         }
     }
 }
@@ -1194,10 +1198,9 @@ struct UpdateKernel {
                 }
             }
         } else {
-            // BF16-tail form: the row kind is uniform, so each velocity takes
-            // one branch into a copy of the body specialised for FP32 or BF16
-            // rows (one straight-line body per kind schedules its loads as
-            // well as the FP32 form does); no recurrence for the equilibria
+            // BF16-tail form: the row kind is uniform, so each velocity runs a
+            // copy of the body specialised for FP32 or BF16 rows; no
+            // recurrence for the equilibria
             auto one = [&](int i, long long off, auto half) __attribute__((always_inline)) {
                 constexpr bool H = decltype(half)::value;
                 const Vel v = load_vel(P.vel, i);
@@ -1241,10 +1244,17 @@ struct UpdateKernel {
                     }
                 }
             };
+            // the FP32 rows of the slice, then its BF16 rows (every (cell,
+            // velocity) is updated on its own, so the order is free): each
+            // loop holds one straight-line body and the register budget of
+            // the FP32 form
+            for (int i = v0; i < v1; ++i) {
+                const long long o = row_word(P, i);
+                if (!(o & 1)) one(i, o, std::false_type{});
+            }
             for (int i = v0; i < v1; ++i) {
                 const long long o = row_word(P, i);
                 if (o & 1) one(i, o & ~1LL, std::true_type{});
-                else one(i, o, std::false_type{});
             }
         }
     }
