@@ -1303,10 +1303,11 @@ __device__ __forceinline__ T load_uniform(const T* p) {
     static_assert(sizeof(T) % 4 == 0, "descriptor size");
     typedef const __attribute__((address_space(4))) unsigned* const_uptr;
     const const_uptr s = (const_uptr)(const void*)p;
-    T r;
-    unsigned* d = reinterpret_cast<unsigned*>(&r);
+    unsigned words[sizeof(T) / 4];
 #pragma unroll
-    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) d[k] = s[k];
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) words[k] = s[k];
+    T r;
+    __builtin_memcpy(&r, words, sizeof(T));
     return r;
 }
 

@@ -1,7 +1,7 @@
 """GPU parity at the benchmark workloads' full sizes over their long runs,
 against oracle moments stored by tests/golden/make_oracle_references.py
 (which calls only the oracle): the Kelvin-Helmholtz layer (256^2 x 28^2) in
-FP64 after 50 steps and in FP32 and FP64 after its 2000 steps, and the 3-D
+FP64 and FP32 after 50, 1000 and its 2000 steps, and the 3-D
 shear's 16^3-velocity grid on 16^3 cells in FP32 after its 500 steps at
 Kn 1e-3, 1e-1 and 10.  Each run uses the single-problem launch
 configuration the benchmark times; moments are compared at a seeded sample
@@ -59,11 +59,12 @@ def test_kelvin_helmholtz_fp64_50_steps():
 
 
 def test_kelvin_helmholtz_fp32_2000_steps():
-    _check(wl.kelvin_helmholtz(storage="f32"), _ref("kh2d_256_v28"), [50, 2000], {50: 1e-5, 2000: 1e-5})
+    _check(wl.kelvin_helmholtz(storage="f32"), _ref("kh2d_256_v28"), [50, 1000, 2000],
+           {50: 1e-5, 1000: 1e-5, 2000: 1e-5})
 
 
 def test_kelvin_helmholtz_fp64_2000_steps():
-    _check(wl.kelvin_helmholtz(), _ref("kh2d_256_v28"), [2000], {2000: 1e-12})
+    _check(wl.kelvin_helmholtz(), _ref("kh2d_256_v28"), [1000, 2000], {1000: 1e-12, 2000: 1e-12})
 
 
 @pytest.mark.parametrize("kn,tag", [(1e-3, "kn1e-3"), (1e-1, "kn1e-1"), (10.0, "kn10")])
