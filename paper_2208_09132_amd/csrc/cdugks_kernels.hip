@@ -155,16 +155,6 @@ template <typename ST>
 __device__ __forceinline__ double state_ld(const Problem& P, const void* base, int i, long long c) {
     return state_value<ST>(P, i, state_load<ST>(P, base, i, c));
 }
-// the value a store of v at velocity i keeps
-template <typename ST>
-__device__ __forceinline__ double state_round(const Problem& P, int i, double v) {
-    if constexpr (StoreT<ST>::MIXED) {
-        const float f = (float)v;
-        return (row_word(P, i) & 1) ? (double)(float)(__bf16)f : (double)f;
-    } else {
-        return (double)(ST)v;
-    }
-}
 template <typename ST, bool STREAM>
 __device__ __forceinline__ void state_st(const Problem& P, void* base, int i, long long c, double v) {
     if constexpr (StoreT<ST>::MIXED) {
