@@ -221,8 +221,15 @@ def cpu_baseline(prob, budget_s: float = 20.0):
     o.step(1)
     dt = time.perf_counter() - t0
     N = o.N * o.V
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": N / dt, "unit": "phase-space updates/s", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"1 step of the full {prob['n']} x {prob['nv']} workload, FP64, {dt:.2f} s wall"}
+            "sample": f"1 step of the full {prob['n']} x {prob['nv']} workload, FP64, {dt:.2f} s wall",
+            "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def main():
