@@ -56,6 +56,14 @@ def workload(name: str, storage: str):
     raise SystemExit(f"unknown config {name}")
 
 
+def workload_sized(name: str, storage: str, n: int):
+    """The 3-D workload on n^3 cells (the baseline sample of the oracle)."""
+    from paper_2208_09132_amd import workloads as wl
+    if name != "shear3d":
+        raise ValueError(name)
+    return wl.shear3d(n=n, storage=storage)
+
+
 def time_gpu(prob, steps: int, warmup: int, copy_calibration: bool = False):
     import torch
     from paper_2208_09132_amd import cdugks as cd
@@ -207,16 +215,31 @@ def served_run(nreq: int, budget_gb: float = 200.0, max_active: int = 64, chunk:
             "arrival_rate_per_s": 50.0, "budget_gb": budget_gb, "storage": "f32"}
 
 
-def cpu_baseline(prob, budget_s: float = 20.0):
-    """The FP64 oracle on the host cores: one step of the same workload (a
-    smaller tile of cells when one full step would exceed the budget)."""
+# phase-space points the oracle's baseline step may hold (its ghost-extended
+# slope arrays grow as D^3 per point; the 2-D benchmark workload is 5.1e7)
+CPU_SAMPLE_POINTS = 6.0e7
+
+
+def cpu_baseline(config: str, prob):
+    """The FP64 oracle on the host cores: one step of the same workload, or,
+    when that is larger than CPU_SAMPLE_POINTS phase-space points, of the same
+    workload on fewer cells (same velocity grid), halving the cells per axis."""
     from oracle import oracle as orc
     from tests.helpers import oracle_problem
 
     orc.build(force=False)
-    q = oracle_problem(prob)
+    sample = prob
+    n = list(prob["n"])
+    V = int(np.prod(prob["nv"]))
+    while int(np.prod(n)) * V > CPU_SAMPLE_POINTS and max(n) > 4:
+        n = [max(4, k // 2) for k in n]
+        if config == "shear3d":
+            sample = workload_sized(config, prob["storage"], n[0])
+        else:
+            break
+    q = oracle_problem(sample)
     o = orc.Oracle(q)
-    o.init(prob["rho"], prob["u"], prob["T"])
+    o.init(sample["rho"], sample["u"], sample["T"])
     t0 = time.perf_counter()
     o.step(1)
     dt = time.perf_counter() - t0
@@ -228,7 +251,8 @@ def cpu_baseline(prob, budget_s: float = 20.0):
     except OSError:
         pass
     return {"value": N / dt, "unit": "phase-space updates/s", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"1 step of the full {prob['n']} x {prob['nv']} workload, FP64, {dt:.2f} s wall",
+            "sample": f"1 step of the {'full ' if sample is prob else ''}{sample['n']} x {sample['nv']} "
+                      f"workload, FP64, {dt:.2f} s wall",
             "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
@@ -338,7 +362,7 @@ def main():
     out["copy_ceiling_GBps"] = copy_ceiling()
     out["roofline"]["frac_of_copy_ceiling"] = achieved / out["copy_ceiling_GBps"]
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(prob)
+        out["cpu_baseline"] = cpu_baseline(args.config, prob)
     print(json.dumps(out), flush=True)
 
 
