@@ -203,7 +203,9 @@ void cdugks_batch_destroy(cdugks_batch* batch);
  * Continuous batching: requests are admitted while slots and the device
  * memory budget allow, join the running batch at the next chunk boundary,
  * and leave it when their step count is reached; a host thread drives the
- * device.  Thread-safe. */
+ * device that is current on the calling thread at cdugks_server_create (and
+ * hip_stream, if given, must belong to it; NULL: the server makes its own).
+ * Thread-safe. */
 typedef struct cdugks_server cdugks_server;
 
 int cdugks_server_create(size_t hbm_budget, int max_active, int chunk_steps,

@@ -407,6 +407,7 @@ struct cdugks_server {
     int chunk = 100;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int device = 0;  // the creating thread's device; the worker thread runs on it
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Request*> queue;
@@ -421,8 +422,9 @@ struct cdugks_server {
 namespace {
 
 void server_loop(cdugks_server* s) {
-    int dev = 0;
-    (void)hipGetDevice(&dev);
+    // a new thread starts on device 0; a failure here surfaces as the
+    // requests' init errors
+    (void)hipSetDevice(s->device);
     cdugks_batch* batch = nullptr;
     bool dirty = true;
     for (;;) {
@@ -561,6 +563,11 @@ int cdugks_server_create(size_t hbm_budget, int max_active, int chunk_steps, voi
     s->budget = hbm_budget;
     s->max_active = max_active;
     s->chunk = chunk_steps;
+    hipError_t de = hipGetDevice(&s->device);
+    if (de != hipSuccess) {
+        delete s;
+        return hip_fail(de, "get device");
+    }
     s->stream = (hipStream_t)hip_stream;
     if (!s->stream) {
         hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
