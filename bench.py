@@ -304,7 +304,7 @@ def main():
     ups = N * V * args.steps / wall
     ms_step = 1e3 * wall / args.steps
 
-    # dominant kernel: the update (reads and writes g, b)
+    # dominant kernel: the phase with the longest average duration
     dom = int(np.argmax(phase_ms))
     dom_name = PHASES[dom]
     kb = KERNEL_BYTES.get(dom_name, {"f64": 0.0})["f64"]
