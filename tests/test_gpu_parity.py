@@ -15,7 +15,7 @@ import pytest
 
 from paper_2208_09132_amd import cdugks as cd
 from paper_2208_09132_amd import workloads as wl
-from tests.helpers import make_oracle, moment_errors
+from tests.helpers import make_oracle, moment_errors, patch_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -150,6 +150,31 @@ def test_3d_full_size_fp32_conservation_and_stationarity():
     Wb = s.conserved()
     s.close()
     assert np.array_equal(Wa, Wb)
+
+
+def test_3d_full_size_five_steps_at_a_cell():
+    """The 3-D workload at full size (64^3 cells x 16^3 velocities) for 5
+    steps, FP64 and FP32 storage, in the launch configuration the benchmark
+    times, against the oracle at one cell: the oracle steps only the block of
+    cells within 15 of it (the 5-step reach), with outflow ends, which gives
+    that cell's full-grid result exactly (its CPU test pins this).  The cell
+    sits where the shear gradient is largest, so the block wraps across the
+    periodic y boundary."""
+    p = wl.shear3d(storage="f64")
+    centre = [37, 0, 21]
+    steps = 5
+    q, full_idx, local = patch_problem(p, centre, 3 * steps)
+    _log(f"3-D full size at cell {centre}: oracle on a {q['n']} block, {steps} steps")
+    ref = None
+    for storage, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        _log(f"  GPU {storage}, 64^3 x 16^3, {steps} steps")
+        got, dt = gpu_run(dict(p, storage=storage), steps)
+        if ref is None:
+            r = oracle_run(q, dt, steps)
+            ref = (r[0][local], r[1][:, local], r[2][local])
+        errs = moment_errors(ref, (got[0][full_idx], got[1][:, full_idx], got[2][full_idx]))
+        _log(f"  {storage}: errors rho/u/T = {errs}")
+        assert max(errs) <= tol, (storage, errs)
 
 
 def test_fp32_storage_within_1e5():
