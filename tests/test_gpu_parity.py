@@ -154,7 +154,7 @@ def test_3d_full_size_fp32_conservation_and_stationarity():
 
 def test_3d_full_size_five_steps_at_a_cell():
     """The 3-D workload at full size (64^3 cells x 16^3 velocities) for 5
-    steps, FP64 and FP32 storage, in the launch configuration the benchmark
+    steps, FP64, FP32 and BF16-tail storage, in the launch configuration the benchmark
     times, against the oracle at one cell: the oracle steps only the block of
     cells within 15 of it (the 5-step reach), with outflow ends, which gives
     that cell's full-grid result exactly (its CPU test pins this).  The cell
@@ -166,7 +166,7 @@ def test_3d_full_size_five_steps_at_a_cell():
     q, full_idx, local = patch_problem(p, centre, 3 * steps)
     _log(f"3-D full size at cell {centre}: oracle on a {q['n']} block, {steps} steps")
     ref = None
-    for storage, tol in (("f64", 1e-12), ("f32", 1e-5)):
+    for storage, tol in (("f64", 1e-12), ("f32", 1e-5), ("f32_bf16tail", 1e-5)):
         _log(f"  GPU {storage}, 64^3 x 16^3, {steps} steps")
         got, dt = gpu_run(dict(p, storage=storage), steps)
         if ref is None:
