@@ -177,6 +177,23 @@ def test_3d_full_size_five_steps_at_a_cell():
         assert max(errs) <= tol, (storage, errs)
 
 
+@pytest.mark.parametrize("kn", [1e-1, 10.0])
+def test_3d_full_size_other_knudsen_numbers_at_a_cell(kn):
+    """The 3-D workload's other Knudsen numbers at full size (FP32 storage,
+    2 steps) against the oracle on the 13^3 block within the 2-step reach of
+    a corner cell (the block wraps across the periodic x and z ends)."""
+    p = wl.shear3d(storage="f32", Kn=kn)
+    centre, steps = [63, 31, 0], 2
+    q, full_idx, local = patch_problem(p, centre, 3 * steps)
+    _log(f"3-D full size, Kn {kn}, at cell {centre}: {steps} steps, oracle on a {q['n']} block")
+    got, dt = gpu_run(p, steps)
+    r = oracle_run(q, dt, steps)
+    errs = moment_errors((r[0][local], r[1][:, local], r[2][local]),
+                         (got[0][full_idx], got[1][:, full_idx], got[2][full_idx]))
+    _log(f"  errors rho/u/T = {errs}")
+    assert max(errs) <= 1e-5, errs
+
+
 def test_fp32_storage_within_1e5():
     p = wl.kelvin_helmholtz(n=40, nv=12, storage="f32")
     check_parity(p, 20, 1e-5)
