@@ -126,11 +126,12 @@ hipError_t launch_cell_close_batched(const Problem* probs, const long long* offs
 // (0 when no device answers).
 int tile_blocks_per_cu(int D, int storage, bool update);
 
-// Tile extents per dimension (256 cells per workgroup).
-inline void tile_extent(int D, int t[3]) {
+// Tile extents per dimension (256 cells per workgroup); must match the
+// kernels' Tile<D>.
+constexpr void tile_extent(int D, int t[3]) {
     if (D == 1) { t[0] = 256; t[1] = 1; t[2] = 1; }
     else if (D == 2) { t[0] = 16; t[1] = 16; t[2] = 1; }
-    else { t[0] = 8; t[1] = 8; t[2] = 4; }
+    else { t[0] = 16; t[1] = 4; t[2] = 4; }
 }
 
 }  // namespace cdg

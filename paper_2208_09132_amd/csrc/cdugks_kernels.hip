@@ -355,7 +355,20 @@ __global__ __launch_bounds__(WG) void k_init_phi(Problem P) {
 template <int D> struct Tile;
 template <> struct Tile<1> { static constexpr int X = 256, Y = 1, Z = 1; };
 template <> struct Tile<2> { static constexpr int X = 16, Y = 16, Z = 1; };
-template <> struct Tile<3> { static constexpr int X = 8, Y = 8, Z = 4; };
+// 3-D: 16 cells along x, so that a row of the q box (21 cells) spans whole
+// 128-byte lines in FP32 (an 8-wide tile fetched 17x the field bytes of the
+// 3-D FP32 face sums from HBM; 16 x 4 x 4 halves the kernel's time).  Must
+// match tile_extent on the host.
+template <> struct Tile<3> { static constexpr int X = 16, Y = 4, Z = 4; };
+
+template <int D>
+constexpr bool tile_matches_host() {
+    int t[3] = {0, 0, 0};
+    tile_extent(D, t);
+    return t[0] == Tile<D>::X && t[1] == Tile<D>::Y && t[2] == Tile<D>::Z;
+}
+static_assert(tile_matches_host<1>() && tile_matches_host<2>() && tile_matches_host<3>(),
+              "the host's tile_extent and the kernels' Tile<D> differ");
 
 // XCD-aware order: consecutive workgroup ids are spread over the 8 XCDs, so
 // give each XCD a contiguous block of the (tile, slice) space; neighbouring
