@@ -181,7 +181,10 @@ int cdugks_info(cdugks_ctx* ctx, double* dt, double* t, int64_t* steps);
  * step: face sums, face closure, cell closure, update.  Waits for the stream. */
 int cdugks_profile_phases(cdugks_ctx* ctx, int64_t nsteps, double* ms);
 
-/* Release the context (waits for its stream).  NULL-safe. */
+/* Release the context (waits for its stream).  NULL-safe.  A context that
+ * belongs to a live batch is NOT released (the batch's graphs refer to its
+ * memory): the call then only sets cdugks_last_error (CDUGKS_ERR_BUSY) and
+ * the context stays valid; destroy the batch first. */
 void cdugks_destroy(cdugks_ctx* ctx);
 
 /* ---------------- batched form -------------------------------------------
@@ -208,6 +211,8 @@ void cdugks_batch_destroy(cdugks_batch* batch);
  * Thread-safe. */
 typedef struct cdugks_server cdugks_server;
 
+/* chunk_steps: steps per admission round (rounded up to an even count, the
+ * batch's graph chunk). */
 int cdugks_server_create(size_t hbm_budget, int max_active, int chunk_steps,
                          void* hip_stream, cdugks_server** out);
 /* Copies the request.  CDUGKS_ERR_TOO_LARGE if it can never fit the budget. */

@@ -229,6 +229,7 @@ class Solver:
         self.V = int(np.prod([prob["nv"][d] for d in range(self.D)]))
         self._arena = None
         self._stream = None
+        self._batch = None  # the live Batch this solver belongs to, if any
         arena, nbytes = None, 0
         if use_torch:
             import torch
@@ -242,6 +243,10 @@ class Solver:
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
+            b = getattr(self, "_batch", None)
+            if b is not None and getattr(b, "h", None) is not None:
+                # the library refuses too (the batch refers to this context)
+                raise CdugksError(ERR_BUSY, "solver belongs to a live batch; close the batch first")
             cdugks_destroy(self.ctx)
             self.ctx = None
         self._arena = None
@@ -317,6 +322,8 @@ class Batch:
         h = ctypes.c_void_p()
         check(load_library().cdugks_batch_create(arr, len(self.solvers), int(chunk_steps), ctypes.byref(h)))
         self.h = h
+        for sv in self.solvers:
+            sv._batch = self
 
     def step(self, n: int) -> None:
         check(load_library().cdugks_batch_step(self.h, int(n)))
@@ -325,6 +332,9 @@ class Batch:
         if getattr(self, "h", None) is not None:
             load_library().cdugks_batch_destroy(self.h)
             self.h = None
+            for sv in self.solvers:
+                if sv._batch is self:
+                    sv._batch = None
 
     def __del__(self):
         try:

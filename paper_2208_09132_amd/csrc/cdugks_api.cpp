@@ -802,6 +802,12 @@ int cdugks_profile_phases(cdugks_ctx* c, int64_t nsteps, double* ms) {
 
 void cdugks_destroy(cdugks_ctx* c) {
     if (!c) return;
+    if (c->in_batch) {
+        // the batch's captured graphs and device problem table point into
+        // this context's memory: refuse, and leave the context intact
+        fail(CDUGKS_ERR_BUSY, "context belongs to a batch (destroy the batch first); not destroyed");
+        return;
+    }
     (void)hipStreamSynchronize(c->stream);
     for (int k = 0; k < 2; ++k)
         if (c->graph[k]) (void)hipGraphExecDestroy(c->graph[k]);

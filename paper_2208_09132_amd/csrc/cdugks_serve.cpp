@@ -562,7 +562,9 @@ int cdugks_server_create(size_t hbm_budget, int max_active, int chunk_steps, voi
     if (!s) return fail(CDUGKS_ERR_NOMEM, "host allocation failed");
     s->budget = hbm_budget;
     s->max_active = max_active;
-    s->chunk = chunk_steps;
+    // even, like a batch's graph chunk: a full chunk then replays the
+    // captured graph instead of launching its steps one by one
+    s->chunk = chunk_steps + (chunk_steps & 1);
     hipError_t de = hipGetDevice(&s->device);
     if (de != hipSuccess) {
         delete s;

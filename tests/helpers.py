@@ -20,6 +20,15 @@ def oracle_dt(prob):
     return orc.cfl_dt(prob.get("cfl", 0.5), dx, xi_max(prob))
 
 
+def dt_checked(prob, gpu_dt):
+    """The oracle's own static CFL step (Sec. 4) for prob, after checking that
+    the library resolved the same step (to rounding).  Parity runs step the
+    oracle with this value, so a wrong step in the library fails them."""
+    dt = oracle_dt(prob)
+    assert abs(gpu_dt - dt) <= 1e-15 * dt, f"library dt {gpu_dt!r} != oracle dt {dt!r}"
+    return dt
+
+
 def oracle_problem(prob, dt=None):
     q = dict(prob)
     relax = prob.get("relax", "kn")

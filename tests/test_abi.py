@@ -115,3 +115,33 @@ def test_null_context_is_rejected():
     assert lib.cdugks_step(None, 1) == cd.ERR_INVALID
     assert lib.cdugks_sync(None) == cd.ERR_INVALID
     lib.cdugks_destroy(None)  # NULL-safe
+
+
+@pytest.mark.gpu
+def test_destroying_a_batched_context_is_refused():
+    """cdugks_destroy of a context that belongs to a live batch leaves it
+    intact (the batch's graphs refer to its memory) and sets the error text;
+    the batch still steps, and after the batch is gone the context gives the
+    same result as a solo run of the same steps."""
+    p = wl.kelvin_helmholtz(n=24, nv=8)
+    q = wl.sod(n=64, nv=16)
+    ref = cd.Solver(p)
+    ref.step(6)
+    want = ref.moments()
+    ref.close()
+    a, b = cd.Solver(p), cd.Solver(q)
+    bt = cd.Batch([a, b], chunk_steps=2)
+    lib = cd.load_library()
+    lib.cdugks_destroy(a.ctx)  # refused
+    assert "batch" in cd.last_error()
+    with pytest.raises(cd.CdugksError) as ei:
+        a.close()  # the binding refuses as well
+    assert ei.value.code == cd.ERR_BUSY
+    bt.step(4)
+    bt.close()
+    a.step(2)
+    got = a.moments()
+    for x, y in zip(got, want):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()

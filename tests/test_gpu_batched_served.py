@@ -1,6 +1,8 @@
 """GPU tests of the batched and served forms: every problem gives bitwise the
-same result alone and in a mix; a sampled problem matches the oracle; the
-server admits by memory budget and isolates failures."""
+same result alone and in a mix; sampled problems (the batched workload's and
+the served stream's own) match the oracle; the server admits by memory budget,
+refuses invalid requests at submit and retires a request that fails on the
+device without disturbing the others."""
 import ctypes
 import math
 import sys
@@ -11,7 +13,7 @@ import pytest
 
 from paper_2208_09132_amd import cdugks as cd
 from paper_2208_09132_amd import workloads as wl
-from tests.helpers import make_oracle, moment_errors
+from tests.helpers import dt_checked, make_oracle, moment_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -90,7 +92,7 @@ def test_batched_sample_matches_oracle():
     b.close()
     for p, s in zip(probs, solvers):
         got = s.moments()
-        o = make_oracle(p, dt=s.dt)
+        o = make_oracle(p, dt=dt_checked(p, s.dt))
         assert o.step(8) == 0
         errs = moment_errors(o.moments(), got)
         tol = 1e-12 if p["storage"] == "f64" else 1e-5
@@ -125,7 +127,7 @@ def test_batched_workload_equals_alone_and_matches_oracle():
         idx = sorted((k for k, p in enumerate(probs) if p["dim"] == dim), key=lambda k: cost[k])
         sample += idx[:4]
     for k in sample:
-        o = make_oracle(probs[k], dt=dts[k])
+        o = make_oracle(probs[k], dt=dt_checked(probs[k], dts[k]))
         assert o.step(steps) == 0
         errs = moment_errors(o.moments(), got[k])
         _log(f"batched workload vs oracle: problem {k} dim={probs[k]['dim']} errs={errs}")
@@ -179,16 +181,114 @@ def test_server_results_equal_alone_and_budget_admission():
     srv.close()
 
 
-def test_server_isolates_a_failing_request():
+def _serve(srv, probs, steps, timeout=120.0):
+    """Submit every problem, then poll until all are done; returns the poll
+    results (or the CdugksError a failed request raised) by position."""
+    tickets = [srv.submit(p, n) for p, n in zip(probs, steps)]
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets) and time.time() - t0 < timeout:
+        for k, t in enumerate(tickets):
+            if k in done:
+                continue
+            try:
+                r = srv.poll(t)
+            except cd.CdugksError as e:
+                r = e
+            if r is not None:
+                done[k] = r
+        time.sleep(0.005)
+    assert len(done) == len(tickets), f"{len(tickets) - len(done)} requests still pending"
+    return [done[k] for k in range(len(tickets))]
+
+
+def test_served_stream_requests_equal_alone_and_match_oracle():
+    """The served workload's own requests: the first six of the seeded Poisson
+    stream (Gresho vortices and random-Fourier states, 271^2..434^2 cells x
+    16^2..30^2 velocities, FP32 storage), their step counts cut to 9..20 so
+    that they end at different chunk boundaries, under a memory budget that
+    admits only some at a time.  Each result is bitwise equal to the same
+    request stepped alone, and the two cheapest (both vortices) match the FP64
+    oracle within the FP32 tolerance, 1e-5."""
+    stream = wl.served_stream(count=6)
+    probs = [p for _, p in stream]
+    steps = [20, 14, 17, 9, 12, 16]
+    vortex = [k for k, p in enumerate(probs) if p["vmax"][0] == 10.0]
+    assert len(vortex) >= 2
+    need = [cd.cdugks_required_bytes(p) for p in probs]
+    budget = int(max(need) * 1.5)  # the largest request fits, but never all at once
+    assert sum(need) > budget
+    _log(f"served stream prefix: {[p['n'][0] for p in probs]} cells per axis, budget {budget / 1e9:.1f} GB")
+    solo, dts = [], []
+    for p, n in zip(probs, steps):
+        s = cd.Solver(p)
+        s.step(n)
+        solo.append(s.moments())
+        dts.append(s.dt)
+        s.close()
+    srv = cd.Server(budget, max_active=4, chunk_steps=4)
+    res = _serve(srv, probs, steps)
+    srv.close()
+    for k, (r, ref) in enumerate(zip(res, solo)):
+        assert not isinstance(r, Exception), (k, r)
+        rho, u, T, tq, ts = r
+        assert np.array_equal(rho, ref[0]) and np.array_equal(u, ref[1]) and np.array_equal(T, ref[2]), k
+        assert tq >= 0 and ts > 0
+    cost = [int(np.prod(p["n"])) * int(np.prod(p["nv"])) * n for p, n in zip(probs, steps)]
+    for k in sorted(range(len(probs)), key=lambda j: cost[j])[:2]:
+        _log(f"  request {k}: oracle {probs[k]['n']} x {probs[k]['nv']}, {steps[k]} steps")
+        o = make_oracle(probs[k], dt=dt_checked(probs[k], dts[k]))
+        assert o.step(steps[k]) == 0
+        errs = moment_errors(o.moments(), res[k][:3])
+        _log(f"  request {k} ({'vortex' if k in vortex else 'random Fourier'}) vs oracle: errs={errs}")
+        assert max(errs) <= 1e-5, (k, errs)
+
+
+def _cold_request():
+    """A state colder than the velocity grid resolves: every discrete
+    equilibrium value underflows to zero, so the first step's face densities
+    vanish and the step raises the non-physical flag on the device (the
+    request is accepted at submit: its moments are valid)."""
+    p = wl.random_fourier(2, [20, 20], [8, 8], wl.SplitMix64(3), amp=0.0, Kn=1e-2)
+    p["T"] = np.full(400, 1e-4)
+    p["u"] = np.stack([np.full(400, 0.3), np.full(400, 0.2)])
+    return p
+
+
+def test_server_isolates_a_request_failing_mid_run():
+    """A request that turns non-physical on the device during its first chunk
+    is retired with CDUGKS_ERR_NONPHYSICAL while the requests batched with it
+    run on, bitwise equal to their solo runs."""
+    good = mixed_problems(seed=9, count=3)
+    bad = _cold_request()
+    s = cd.Solver(bad)  # alone it fails the same way
+    s.step(1)
+    with pytest.raises(cd.CdugksError) as ei:
+        s.sync()
+    assert ei.value.code == cd.ERR_NONPHYSICAL
+    s.close()
+    probs = [good[0], bad, good[1], good[2]]
+    steps = [9, 9, 6, 9]
+    srv = cd.Server(1 << 34, max_active=4, chunk_steps=3)
+    res = _serve(srv, probs, steps)
+    srv.close()
+    assert isinstance(res[1], cd.CdugksError) and res[1].code == cd.ERR_NONPHYSICAL, res[1]
+    for k in (0, 2, 3):
+        ref = alone(probs[k], steps[k])
+        assert np.array_equal(res[k][0], ref[0]) and np.array_equal(res[k][2], ref[2]), k
+
+
+def test_server_refuses_an_invalid_request_at_submit():
     good = mixed_problems(seed=9, count=3)
     bad = dict(good[0])
     bad["rho"] = good[0]["rho"].copy()
-    bad["rho"][2] = -1.0  # rejected when the server initialises it
+    bad["rho"][2] = -1.0
     srv = cd.Server(1 << 34, max_active=4, chunk_steps=3)
     tg = [srv.submit(p, 5) for p in good]
-    with pytest.raises(cd.CdugksError):
-        # the host validation already refuses it at submit time
+    with pytest.raises(cd.CdugksError) as ei:
+        # the host validation refuses it at submit time
         srv.submit(bad, 5)
+    assert ei.value.code == cd.ERR_INVALID
     for t, p in zip(tg, good):
         r = None
         t0 = time.time()

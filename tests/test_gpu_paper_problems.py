@@ -16,7 +16,7 @@ import pytest
 from paper_2208_09132_amd import cdugks as cd
 from paper_2208_09132_amd import workloads as wl
 from tests import reference_solutions as rs
-from tests.helpers import moment_errors
+from tests.helpers import dt_checked, moment_errors
 from tests.test_gpu_parity import _log, check_parity, oracle_run
 
 pytestmark = pytest.mark.gpu
@@ -47,7 +47,7 @@ def test_sod_validation_paper_size():
     s = cd.Solver(p)
     s.step(64)
     got = s.moments()
-    ref = oracle_run(p, s.dt, 64)
+    ref = oracle_run(p, dt_checked(p, s.dt), 64)
     errs = moment_errors(ref, got, 1.4, 0.5)
     _log(f"  64 steps: errors rho/u/T = {errs}")
     assert max(errs) <= 1e-12, errs
@@ -89,7 +89,7 @@ def test_thermoacoustic_wave_paper_size():
         rho0, u0, T0f = s.moments()
         a0, _, c0 = _fundamental(x, k, rho0, u0[0], T0f)
         s.step(200)
-        errs = moment_errors(oracle_run(p, s.dt, 200), s.moments(), p["gamma"], p["R"])
+        errs = moment_errors(oracle_run(p, dt_checked(p, s.dt), 200), s.moments(), p["gamma"], p["R"])
         _log(f"  200 steps: errors rho/u/T = {errs}")
         assert max(errs) <= 1e-12, errs
         times, got = [], []
@@ -122,7 +122,7 @@ def test_sine_wave_paper_size():
     s = cd.Solver(p)
     W0 = s.conserved().sum(axis=0)
     s.step(20)
-    errs = moment_errors(oracle_run(p, s.dt, 20), s.moments(), p["gamma"], p["R"])
+    errs = moment_errors(oracle_run(p, dt_checked(p, s.dt), 20), s.moments(), p["gamma"], p["R"])
     _log(f"  20 steps: errors rho/u/T = {errs}")
     assert max(errs) <= 1e-12, errs
     s.step(p["steps"] - 20)

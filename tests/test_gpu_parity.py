@@ -15,7 +15,7 @@ import pytest
 
 from paper_2208_09132_amd import cdugks as cd
 from paper_2208_09132_amd import workloads as wl
-from tests.helpers import make_oracle, moment_errors, patch_problem
+from tests.helpers import dt_checked, make_oracle, moment_errors, patch_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,8 @@ def oracle_run(prob, dt, steps):
 def check_parity(prob, steps, tol):
     _log(f"parity: dim={prob['dim']} n={prob['n']} nv={prob['nv']} bc={prob['bc']} storage={prob.get('storage')} steps={steps}")
     got, dt = gpu_run(prob, steps)
-    ref = oracle_run(prob, dt, steps)
+    # the oracle steps with its own CFL step, checked against the library's
+    ref = oracle_run(prob, dt_checked(prob, dt), steps)
     errs = moment_errors(ref, got, prob.get("gamma", 5.0 / 3.0), prob.get("R", 0.5))
     _log(f"  errors rho/u/T = {errs}")
     assert max(errs) <= tol, errs
@@ -170,7 +171,8 @@ def test_3d_full_size_five_steps_at_a_cell():
         _log(f"  GPU {storage}, 64^3 x 16^3, {steps} steps")
         got, dt = gpu_run(dict(p, storage=storage), steps)
         if ref is None:
-            r = oracle_run(q, dt, steps)
+            # the block steps with the full problem's oracle-side step
+            r = oracle_run(q, dt_checked(p, dt), steps)
             ref = (r[0][local], r[1][:, local], r[2][local])
         errs = moment_errors(ref, (got[0][full_idx], got[1][:, full_idx], got[2][full_idx]))
         _log(f"  {storage}: errors rho/u/T = {errs}")
@@ -187,7 +189,7 @@ def test_3d_full_size_other_knudsen_numbers_at_a_cell(kn):
     q, full_idx, local = patch_problem(p, centre, 3 * steps)
     _log(f"3-D full size, Kn {kn}, at cell {centre}: {steps} steps, oracle on a {q['n']} block")
     got, dt = gpu_run(p, steps)
-    r = oracle_run(q, dt, steps)
+    r = oracle_run(q, dt_checked(p, dt), steps)
     errs = moment_errors((r[0][local], r[1][:, local], r[2][local]),
                          (got[0][full_idx], got[1][:, full_idx], got[2][full_idx]))
     _log(f"  errors rho/u/T = {errs}")

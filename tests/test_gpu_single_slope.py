@@ -9,7 +9,7 @@ import pytest
 
 from paper_2208_09132_amd import cdugks as cd
 from paper_2208_09132_amd import workloads as wl
-from tests.helpers import make_oracle, moment_errors
+from tests.helpers import dt_checked, make_oracle, moment_errors
 
 pytestmark = pytest.mark.gpu
 SS = "single_slope"
@@ -28,7 +28,7 @@ def _parity(prob, steps, tol):
     got = s.moments()
     dt = s.dt
     s.close()
-    o = make_oracle(prob, dt=dt)
+    o = make_oracle(prob, dt=dt_checked(prob, dt))
     assert o.step(steps) == 0
     errs = moment_errors(o.moments(), got, prob.get("gamma", 5.0 / 3.0), prob.get("R", 0.5))
     _log(f"  errors rho/u/T = {errs}")
