@@ -167,6 +167,22 @@ int cdugks_conserved(cdugks_ctx* ctx, double* W);
  * to host, V = nv[0]*nv[1]*nv[2] with the velocity index x fastest. */
 int cdugks_distributions(cdugks_ctx* ctx, double* g, double* b);
 
+/* ---------------- allocation-free read-out --------------------------------
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the same FP64 copies of g and b as
+ * cdugks_distributions (bitwise), staged through a fixed device array of
+ * CDUGKS_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it
+ * runs on until the process ends, instead of a temporary allocation.  Calls
+ * no hipMalloc, hipFree or other allocating routine.  Copies the velocity
+ * rows in passes of as many rows as the array holds, on the context's stream
+ * and device, and waits.  CDUGKS_ERR_TOO_LARGE (nothing copied) when one
+ * velocity row of N FP64 values exceeds the array, i.e. N > 4194304 cells.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (nothing in it needs to start at zero); calls from threads of one
+ * process are serialised by a lock, so they do not race on it. */
+#define CDUGKS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int cdugks_distributions_noalloc(cdugks_ctx* ctx, double* g, double* b);
+
 /* Storage of the context's distributions: the number of velocity rows held
  * in BF16 (0 unless CDUGKS_STORE_F32_BF16TAIL) and the bytes of one state
  * array (g or b) as laid out.  Either pointer may be NULL. */

@@ -84,6 +84,7 @@ def load_library():
         "cdugks_moments": (ctypes.c_int, [vp, _DP, _DP, _DP, ctypes.c_int]),
         "cdugks_conserved": (ctypes.c_int, [vp, _DP]),
         "cdugks_distributions": (ctypes.c_int, [vp, _DP, _DP]),
+        "cdugks_distributions_noalloc": (ctypes.c_int, [vp, _DP, _DP]),
         "cdugks_info": (ctypes.c_int, [vp, _DP, _DP, ctypes.POINTER(i64)]),
         "cdugks_storage_info": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(sz)]),
         "cdugks_profile_phases": (ctypes.c_int, [vp, i64, _DP]),

@@ -15,6 +15,23 @@ namespace cdg {
 
 static thread_local std::string g_last_error;
 
+// ---------------------------------------------------------------------------
+// Fixed device staging array of the allocation-free read-out
+// (cdugks_distributions_noalloc).  Every GPU the library runs on holds its
+// own copy until the process ends.  On the host the name is only a stand-in
+// for the symbol, never a device address: host code passes the address that
+// hipGetSymbolAddress returns for the current device (looked up once per
+// device, on the entry point's first call there) to kernels and copies.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[CDUGKS_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;               // serialises the calls that use the array
+static double* g_scratch_dev[MAX_DEVICES];    // device address per device (null: not looked up)
+
+// The array's device address on `dev`, which must be current; g_scratch_mu held.
+static int scratch_on_device(int dev, double** out);
+
 int fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -509,6 +526,18 @@ static hipError_t capture_steps(cdugks_ctx* c, int cur, int steps, hipGraphExec_
     return e;
 }
 
+static int scratch_on_device(int dev, double** out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(CDUGKS_ERR_DEVICE, "device %d outside the scratch table", dev);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch array address");
+        g_scratch_dev[dev] = (double*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return CDUGKS_OK;
+}
+
 }  // namespace cdg
 
 using namespace cdg;
@@ -553,6 +582,10 @@ int cdugks_init(const cdugks_space* space, const cdugks_velocity* vel, const cdu
     c->r = r;
     c->stream = (hipStream_t)hip_stream;
     hipError_t e;
+    if ((e = hipGetDevice(&c->device)) != hipSuccess) {
+        delete c;
+        return hip_fail(e, "get device");
+    }
     if (!c->stream) {
         // a private stream (default priority): graphs cannot be captured on
         // the legacy null stream
@@ -596,12 +629,12 @@ int cdugks_init(const cdugks_space* space, const cdugks_velocity* vel, const cdu
     if (r.any_dirichlet) dirichlet_tables(r, veltab, dirtab);
     std::vector<long long> rowtab;
     if (r.storage == CDUGKS_STORE_F32_BF16TAIL) c->bf16_rows = tail_rows(r, veltab, u, T, rowtab);
-    // moments staged in the scratch region for the init kernel
+    // moments staged in the arena's staging region for the init kernel
     std::vector<double> stage((size_t)(r.D + 2) * r.N);
     std::memcpy(stage.data(), rho, sizeof(double) * r.N);
     std::memcpy(stage.data() + r.N, u, sizeof(double) * r.D * r.N);
     std::memcpy(stage.data() + (size_t)(r.D + 1) * r.N, T, sizeof(double) * r.N);
-    double* scratch = (double*)(c->base + r.off_scratch);
+    double* stage_dev = (double*)(c->base + r.off_scratch);
     int zero[64] = {0};
     if ((e = hipMemcpyAsync(c->base + r.off_vel, veltab.data(), veltab.size() * 8, hipMemcpyHostToDevice,
                             c->stream)) != hipSuccess ||
@@ -611,7 +644,7 @@ int cdugks_init(const cdugks_space* space, const cdugks_velocity* vel, const cdu
                                                  hipMemcpyHostToDevice, c->stream)) != hipSuccess) ||
         (!rowtab.empty() && (e = hipMemcpyAsync(c->base + r.off_rows, rowtab.data(), rowtab.size() * 8,
                                                  hipMemcpyHostToDevice, c->stream)) != hipSuccess) ||
-        (e = hipMemcpyAsync(scratch, stage.data(), stage.size() * 8, hipMemcpyHostToDevice, c->stream)) !=
+        (e = hipMemcpyAsync(stage_dev, stage.data(), stage.size() * 8, hipMemcpyHostToDevice, c->stream)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(c->base + r.off_err, zero, sizeof zero, hipMemcpyHostToDevice, c->stream)) !=
             hipSuccess) {
@@ -621,7 +654,7 @@ int cdugks_init(const cdugks_space* space, const cdugks_velocity* vel, const cdu
     c->cur = 0;
     Problem P = c->P;
     set_pingpong(P, r, c->base, 0);
-    if ((e = launch_init(P, scratch, scratch + r.N, scratch + (size_t)(r.D + 1) * r.N, c->stream)) !=
+    if ((e = launch_init(P, stage_dev, stage_dev + r.N, stage_dev + (size_t)(r.D + 1) * r.N, c->stream)) !=
         hipSuccess) {
         cdugks_destroy(c);
         return hip_fail(e, "init kernels");
@@ -749,12 +782,47 @@ int cdugks_distributions(cdugks_ctx* c, double* g, double* b) {
     double* outs[2] = {g, b};
     size_t offs[2] = {r.off_g[c->cur], r.off_b[c->cur]};
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
-        e = launch_to_f64(c->P, c->base + offs[k], tmp, c->stream);
+        e = launch_to_f64(c->P, c->base + offs[k], 0, (int)r.V, tmp, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e == hipSuccess) e = hipMemcpy(outs[k], tmp, n * 8, hipMemcpyDeviceToHost);
     }
     (void)hipFree(tmp);
     return e == hipSuccess ? CDUGKS_OK : hip_fail(e, "distribution copy");
+}
+
+int cdugks_distributions_noalloc(cdugks_ctx* c, double* g, double* b) {
+    if (!c || !g || !b) return fail(CDUGKS_ERR_INVALID, "null argument");
+    const Resolved& r = c->r;
+    const size_t row_bytes = (size_t)r.N * sizeof(double);
+    const long long per_pass = (long long)(CDUGKS_NOALLOC_SCRATCH_BYTES / row_bytes);
+    if (per_pass < 1)
+        return fail(CDUGKS_ERR_TOO_LARGE,
+                    "a velocity row of %lld cells (%zu bytes as FP64) exceeds the %zu-byte scratch array",
+                    (long long)r.N, row_bytes, (size_t)CDUGKS_NOALLOC_SCRATCH_BYTES);
+    int rc = cdugks_sync(c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e == hipSuccess && prev != c->device) e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "select the context's device");
+    double* buf = nullptr;
+    rc = scratch_on_device(c->device, &buf);
+    double* outs[2] = {g, b};
+    const size_t offs[2] = {r.off_g[c->cur], r.off_b[c->cur]};
+    for (int k = 0; k < 2 && rc == CDUGKS_OK; ++k) {
+        for (long long i0 = 0; i0 < r.V && rc == CDUGKS_OK; i0 += per_pass) {
+            const int nr = (int)std::min<long long>(per_pass, r.V - i0);
+            e = launch_to_f64(c->P, c->base + offs[k], (int)i0, nr, buf, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(outs[k] + (size_t)i0 * r.N, buf, (size_t)nr * row_bytes, hipMemcpyDeviceToHost,
+                                   c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) rc = hip_fail(e, "distribution copy through the scratch array");
+        }
+    }
+    if (prev >= 0 && prev != c->device) (void)hipSetDevice(prev);
+    return rc;
 }
 
 int cdugks_info(cdugks_ctx* c, double* dt, double* t, int64_t* steps) {

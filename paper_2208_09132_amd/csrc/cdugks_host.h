@@ -59,6 +59,7 @@ struct cdugks_ctx {
     cdg::Problem P;       // descriptor without the ping-pong pointers
     hipStream_t stream = nullptr;
     bool own_stream = false;  // created here when the caller passes NULL
+    int device = 0;           // the device current at cdugks_init
     char* base = nullptr;
     bool own_memory = false;
     int cur = 0;          // buffer parity holding the current state

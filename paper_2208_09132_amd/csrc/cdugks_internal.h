@@ -101,7 +101,8 @@ hipError_t launch_cell_close(const Problem& P, hipStream_t s);
 hipError_t launch_update(const Problem& P, hipStream_t s);
 hipError_t launch_moments(const Problem& P, const double* W, double* rho, double* u, double* T,
                           hipStream_t s);
-hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStream_t s);
+// velocity rows [row0, row0 + nrows) of a state array as FP64 into dst[nrows][N]
+hipError_t launch_to_f64(const Problem& P, const void* src, int row0, int nrows, double* dst, hipStream_t s);
 
 // Batched: one launch per phase across problems of one class (storage,
 // whether they have Dirichlet sides, and the reconstruction option, which

@@ -1556,13 +1556,14 @@ __global__ __launch_bounds__(WG) void k_moments(Problem P, const double* W, doub
     T[c] = (P.gamma - 1.0) / P.R * (Wv[D + 1] / r - 0.5 * u2);
 }
 
-// a state array ([V][N] in the problem's storage form) as FP64
+// velocity rows [row0, row0 + nrows) of a state array ([V][N] in the
+// problem's storage form) as FP64, dst[nrows][N]
 template <typename ST>
-__global__ __launch_bounds__(WG) void k_to_f64(Problem P, const void* src, double* dst) {
+__global__ __launch_bounds__(WG) void k_to_f64(Problem P, const void* src, int row0, int nrows, double* dst) {
     const long long idx = (long long)blockIdx.x * WG + threadIdx.x;
-    if (idx >= P.N * P.V) return;
+    if (idx >= P.N * nrows) return;
     const long long i = idx / P.N;
-    dst[idx] = state_ld<ST>(P, src, (int)i, idx - i * P.N);
+    dst[idx] = state_ld<ST>(P, src, row0 + (int)i, idx - i * P.N);
 }
 
 // ---------------------------------------------------------------------------
@@ -1674,11 +1675,12 @@ hipError_t launch_moments(const Problem& P, const double* W, double* rho, double
     return hipGetLastError();
 }
 
-hipError_t launch_to_f64(const Problem& P, const void* src, double* dst, hipStream_t s) {
-    const dim3 grid(blocks_for(P.N * P.V));
-    if (P.storage == 0) hipLaunchKernelGGL(k_to_f64<double>, grid, dim3(WG), 0, s, P, src, dst);
-    else if (P.storage == 1) hipLaunchKernelGGL(k_to_f64<float>, grid, dim3(WG), 0, s, P, src, dst);
-    else hipLaunchKernelGGL(k_to_f64<Bf16Tail>, grid, dim3(WG), 0, s, P, src, dst);
+hipError_t launch_to_f64(const Problem& P, const void* src, int row0, int nrows, double* dst, hipStream_t s) {
+    if (row0 < 0 || nrows <= 0 || row0 + nrows > P.V) return hipErrorInvalidValue;
+    const dim3 grid(blocks_for(P.N * nrows));
+    if (P.storage == 0) hipLaunchKernelGGL(k_to_f64<double>, grid, dim3(WG), 0, s, P, src, row0, nrows, dst);
+    else if (P.storage == 1) hipLaunchKernelGGL(k_to_f64<float>, grid, dim3(WG), 0, s, P, src, row0, nrows, dst);
+    else hipLaunchKernelGGL(k_to_f64<Bf16Tail>, grid, dim3(WG), 0, s, P, src, row0, nrows, dst);
     return hipGetLastError();
 }
 
