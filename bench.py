@@ -8,6 +8,9 @@ HBM roofline, the FP32-storage rate of the same workload, and the FP64 CPU
 oracle timed on a bounded sample on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config kh|sod|shear3d]
+
+The default run also times the 3-D shear workload (64^3 cells x 16^3
+velocities, FP32 storage) for a few steps, with its own roofline block.
 """
 from __future__ import annotations
 
@@ -30,19 +33,50 @@ KERNEL_BYTES = {"face_sums": {"f64": 16.0, "f32": 8.0}, "update": {"f64": 32.0, 
 PHASES = ["face_sums", "face_close", "cell_close", "update"]
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_face_sums_kh2d_256_v28_fp64.md")
+# committed rocprofv3 traffic summaries, by (workload, storage, kernel)
+TRAFFIC_PROFILES = {
+    ("kh", "f64", "face_sums"): "hbm_traffic_face_sums_kh2d_256_v28_fp64.md",
+    ("kh", "f64", "update"): "hbm_traffic_update_kh2d_256_v28_fp64.md",
+    ("shear3d", "f32", "face_sums"): "hbm_traffic_face_sums_shear3d_64_v16_fp32.md",
+    ("shear3d", "f32", "update"): "hbm_traffic_update_shear3d_64_v16_fp32.md",
+    ("shear3d", "f64", "face_sums"): "hbm_traffic_face_sums_shear3d_64_v16_fp64.md",
+    ("shear3d", "f64", "update"): "hbm_traffic_update_shear3d_64_v16_fp64.md",
+}
 
 
-def profiled_traffic(config: str, kernel: str):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    PMC summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), or
-    None when that summary was taken from other kernel sources or covers
-    another kernel or workload."""
+def profiled_traffic(config: str, storage: str, kernel: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 PMC
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy kernel), or None
+    when there is none for this workload, storage and kernel, or it was taken
+    from other kernel sources."""
     from paper_2208_09132_amd import profiling as pf
-    rec = pf.load_record(TRAFFIC_PROFILE)
-    if config != "kh" or kernel != "face_sums" or rec is None or rec.get("digest") != pf.source_digest():
+    name = TRAFFIC_PROFILES.get((config, storage, kernel))
+    rec = pf.load_record(os.path.join(ROOT, "profiles", name)) if name else None
+    if rec is None or rec.get("digest") != pf.source_digest():
         return None
     return rec
+
+
+def roofline_block(config: str, storage: str, N: int, V: int, phase_ms, ups: float):
+    """The dominant kernel (longest average duration per step, from HIP events
+    on the context's stream) against the HBM roofline: its algorithmic bytes
+    per launch (the scheme's minimum share of that kernel: g, b read by the
+    face sums; read and written by the update) over its duration."""
+    dom = int(np.argmax(phase_ms))
+    dom_name = PHASES[dom]
+    kb = KERNEL_BYTES.get(dom_name, {storage: 0.0})[storage]
+    achieved = kb * N * V / (phase_ms[dom] * 1e-3) / 1e9
+    rec = profiled_traffic(config, storage, dom_name)
+    return {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": rec["traffic_bytes"] if rec else None,
+            "traffic_unit": "bytes per launch",
+            "traffic_per_update": rec["traffic_bytes"] / (N * V) if rec else None,
+            "kernel_ms": float(phase_ms[dom]), "phase_ms": {k: float(v) for k, v in zip(PHASES, phase_ms)},
+            "algorithmic_bytes_per_update": kb, "units_per_launch": N * V,
+            # the measured HBM traffic of the kernel over its duration
+            "traffic_GBps": rec["traffic_bytes"] / (phase_ms[dom] * 1e-3) / 1e9 if rec else None,
+            "traffic_frac": rec["traffic_bytes"] / (phase_ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS if rec else None,
+            "step_algorithmic_frac": ALGO_BYTES[storage] * ups / 1e9 / HBM_PEAK_GBS}
 
 
 def workload(name: str, storage: str):
@@ -215,15 +249,21 @@ def served_run(nreq: int, budget_gb: float = 200.0, max_active: int = 64, chunk:
             "arrival_rate_per_s": 50.0, "budget_gb": budget_gb, "storage": "f32"}
 
 
-# phase-space points the oracle's baseline step may hold (its ghost-extended
+# phase-space points the oracle's baseline may hold (its ghost-extended
 # slope arrays grow as D^3 per point; the 2-D benchmark workload is 5.1e7)
 CPU_SAMPLE_POINTS = 6.0e7
+# timed oracle steps after one untimed warm-up step, cut short once the timed
+# steps have taken CPU_SAMPLE_SECONDS (never fewer than CPU_MIN_STEPS)
+CPU_TIMED_STEPS = 10
+CPU_MIN_STEPS = 3
+CPU_SAMPLE_SECONDS = 25.0
 
 
 def cpu_baseline(config: str, prob):
-    """The FP64 oracle on the host cores: one step of the same workload, or,
-    when that is larger than CPU_SAMPLE_POINTS phase-space points, of the same
-    workload on fewer cells (same velocity grid), halving the cells per axis."""
+    """The FP64 oracle on the host cores, timed over CPU_TIMED_STEPS steps
+    after one warm-up step, on the same workload, or, when that is larger
+    than CPU_SAMPLE_POINTS phase-space points, on the same workload with fewer
+    cells (same velocity grid), halving the cells per axis."""
     from oracle import oracle as orc
     from tests.helpers import oracle_problem
 
@@ -240,8 +280,15 @@ def cpu_baseline(config: str, prob):
     q = oracle_problem(sample)
     o = orc.Oracle(q)
     o.init(sample["rho"], sample["u"], sample["T"])
+    o.step(1)  # warm-up: first touch of the arrays, thread start-up
     t0 = time.perf_counter()
-    o.step(1)
+    steps = 0
+    while steps < CPU_TIMED_STEPS:
+        if o.step(1) != 0:
+            break
+        steps += 1
+        if steps >= CPU_MIN_STEPS and time.perf_counter() - t0 > CPU_SAMPLE_SECONDS:
+            break
     dt = time.perf_counter() - t0
     N = o.N * o.V
     model = ""
@@ -250,10 +297,23 @@ def cpu_baseline(config: str, prob):
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": N / dt, "unit": "phase-space updates/s", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"1 step of the {'full ' if sample is prob else ''}{sample['n']} x {sample['nv']} "
-                      f"workload, FP64, {dt:.2f} s wall",
+    return {"value": N * steps / dt, "unit": "phase-space updates/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"{steps} steps (after 1 warm-up step) of the {'full ' if sample is prob else ''}"
+                      f"{sample['n']} x {sample['nv']} workload, FP64, {dt:.2f} s wall",
+            "steps": steps, "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
             "cpu_model": model, "host_cpus": os.cpu_count()}
+
+
+def shear3d_leg(steps: int, warmup: int):
+    """The 3-D shear workload (64^3 cells x 16^3 velocities, Kn 1e-3) in its
+    own storage form, FP32 g and b with FP64 moments: updates/s and its
+    dominant kernel against the roofline."""
+    name, p = workload("shear3d", "f32")
+    N, V, wall, ph, _ = time_gpu(p, steps, warmup)
+    ups = N * V * steps / wall
+    return {"workload": name, "value": ups, "unit": "updates/s", "steps": steps, "warmup": warmup,
+            "ms_per_step": 1e3 * wall / steps, "storage": "f32",
+            "roofline": roofline_block("shear3d", "f32", N, V, ph, ups)}
 
 
 def main():
@@ -269,6 +329,9 @@ def main():
     ap.add_argument("--served-requests", type=int, default=16)
     ap.add_argument("--no-sequential", action="store_true",
                     help="skip running the batched leg's problems one by one with the plain step")
+    ap.add_argument("--shear3d-steps", type=int, default=10,
+                    help="timed steps of the 3-D shear leg (FP32, 64^3 x 16^3); 0 skips it")
+    ap.add_argument("--shear3d-warmup", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run the library's FP64 distribution copy (for counter calibration)")
     args = ap.parse_args()
@@ -305,21 +368,8 @@ def main():
     ms_step = 1e3 * wall / args.steps
 
     # dominant kernel: the phase with the longest average duration
-    dom = int(np.argmax(phase_ms))
-    dom_name = PHASES[dom]
-    kb = KERNEL_BYTES.get(dom_name, {"f64": 0.0})["f64"]
-    achieved = kb * N * V / (phase_ms[dom] * 1e-3) / 1e9
-    rec = profiled_traffic(args.config, dom_name)
-    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": rec["traffic_bytes"] if rec else None,
-                "traffic_unit": "bytes per launch",
-                "traffic_per_update": rec["traffic_bytes"] / (N * V) if rec else None,
-                "kernel_ms": float(phase_ms[dom]), "phase_ms": {k: float(v) for k, v in zip(PHASES, phase_ms)},
-                "algorithmic_bytes_per_update": kb,
-                # the measured HBM traffic of the kernel over its duration
-                "traffic_GBps": rec["traffic_bytes"] / (phase_ms[dom] * 1e-3) / 1e9 if rec else None,
-                "traffic_frac": rec["traffic_bytes"] / (phase_ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS if rec else None,
-                "step_algorithmic_frac": ALGO_BYTES["f64"] * ups / 1e9 / HBM_PEAK_GBS}
+    roofline = roofline_block(args.config, "f64", N, V, phase_ms, ups)
+    achieved = roofline["achieved"]
 
     out = {"metric": "phase-space updates/s", "value": ups, "unit": "updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
@@ -359,6 +409,8 @@ def main():
             out["batched"][f"speedup_vs_same_problems_one_by_one_{st}"] = out["batched"]["value"] / seq["value"]
     if args.served_requests > 0:
         out["served"] = served_run(args.served_requests)
+    if args.config != "shear3d" and args.shear3d_steps > 0:
+        out["shear3d_fp32"] = shear3d_leg(args.shear3d_steps, args.shear3d_warmup)
     out["copy_ceiling_GBps"] = copy_ceiling()
     out["roofline"]["frac_of_copy_ceiling"] = achieved / out["copy_ceiling_GBps"]
     if not args.no_cpu:
