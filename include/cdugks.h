@@ -122,6 +122,19 @@ typedef struct {
     int storage;            /* CDUGKS_STORE_* */
     int velocity_slices;    /* velocity-loop split across workgroups; 0 = auto */
     int reconstruction;     /* CDUGKS_RECON_* */
+    int face_tile;          /* face-sum tile shape: 0 = automatic (the autotuner's
+                               choice for the problem's class, else the default);
+                               k >= 1 = the k-th shape of the dimension's list,
+                               cells along (x, y, z) per workgroup:
+                                 dim 1: 256
+                                 dim 2: 16x16, 32x8, 8x32, 32x24
+                                 dim 3: 16x4x4, 32x4x2, 64x2x2, 32x6x4, 64x4x3, 16x8x6
+                               Shapes other than the first need the paper's
+                               reconstruction, no Dirichlet side, and boxes that
+                               fit a CU's LDS in the storage form (the 768-cell
+                               64-wide 3-D shape does not in FP64); else
+                               CDUGKS_ERR_INVALID.  Every shape gives bitwise the
+                               same result. */
 } cdugks_params;
 
 typedef struct cdugks_ctx cdugks_ctx;
@@ -188,6 +201,12 @@ int cdugks_distributions_noalloc(cdugks_ctx* ctx, double* g, double* b);
  * array (g or b) as laid out.  Either pointer may be NULL. */
 int cdugks_storage_info(cdugks_ctx* ctx, int64_t* bf16_rows, size_t* state_array_bytes);
 
+/* Launch shape of the context: its face-sum tile shape (1-based, as in
+ * cdugks_params.face_tile), the velocity slices of the face-sum kernel (which
+ * fix the summation order of the face sums) and of the update kernel.  Any
+ * pointer may be NULL. */
+int cdugks_launch_info(cdugks_ctx* ctx, int* face_tile, int* face_slices, int* update_slices);
+
 /* Time step, simulated time and number of completed steps. */
 int cdugks_info(cdugks_ctx* ctx, double* dt, double* t, int64_t* steps);
 
@@ -243,12 +262,16 @@ void cdugks_server_destroy(cdugks_server* srv);
 
 /* ---------------- autotuner ----------------------------------------------
  * Times candidate launch shapes for the class of this problem (dimension,
- * storage, velocity count, cell-count bucket): the velocity split of the
- * update kernel and the persistent grid size of batched launches.  The
- * fastest is kept in a process-wide table, and written as text to the file
- * named by $CDUGKS_TUNE_CACHE when that is set (read back at first use).  Every
- * candidate computes bitwise the same result, so tuning changes speed only.
- * Advances the context by the steps it times. */
+ * storage, reconstruction, velocity count, cell-count bucket): the face-sum
+ * tile shape (cdugks_params.face_tile's list, the shapes usable for the
+ * problem), the velocity split of the update kernel and the persistent grid
+ * size of batched launches.  The fastest is kept in a process-wide table, and
+ * written as text to the file named by $CDUGKS_TUNE_CACHE when that is set
+ * (read back at first use); contexts created afterwards with face_tile = 0 use
+ * it, and so does this context from its next step.  Every candidate computes
+ * bitwise the same result, so tuning changes speed only.  The context is
+ * advanced by the steps the update and grid trials time (the face-sum trials
+ * rerun the first phase of a step without advancing it). */
 int cdugks_autotune(cdugks_ctx* ctx, int steps_per_trial);
 
 /* Thread-local message describing the last error on this thread. */

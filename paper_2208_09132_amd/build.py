@@ -9,7 +9,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcdugks.so")
-SOURCES = ["cdugks_kernels.hip", "cdugks_api.cpp", "cdugks_serve.cpp"]
+# (source, object name, extra flags): the face-sum unit is compiled once per
+# dimension; all units compile in parallel
+UNITS = [("cdugks_kernels.hip", "cdugks_kernels", []),
+         ("cdugks_face_sums.hip", "cdugks_face_sums_d1", ["-DCDG_FACE_DIM=1"]),
+         ("cdugks_face_sums.hip", "cdugks_face_sums_d2", ["-DCDG_FACE_DIM=2"]),
+         ("cdugks_face_sums.hip", "cdugks_face_sums_d3", ["-DCDG_FACE_DIM=3"]),
+         ("cdugks_batched.hip", "cdugks_batched", []),
+         ("cdugks_api.cpp", "cdugks_api", []),
+         ("cdugks_serve.cpp", "cdugks_serve", [])]
+JOBS = int(os.environ.get("CDUGKS_BUILD_JOBS", "7"))
 ARCH = os.environ.get("CDUGKS_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -24,18 +33,29 @@ HIPCC_FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, src + ".o")
+    cmds, objs = [], []
+    for src, name, extra in UNITS:
+        obj = os.path.join(objdir, name + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [hipcc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append([hipcc, *HIPCC_FLAGS, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True, stderr=None if verbose else subprocess.DEVNULL)
-        objs.append(obj)
+        return subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+    with ThreadPoolExecutor(max_workers=max(1, JOBS)) as ex:
+        results = list(ex.map(run, cmds))
+    for cmd, res in zip(cmds, results):
+        if res.returncode != 0:
+            errs = [ln for ln in res.stderr.splitlines() if "packed-fp32-ops" not in ln]
+            raise RuntimeError("hipcc failed: " + " ".join(cmd) + "\n" + "\n".join(errs[-60:]))
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)

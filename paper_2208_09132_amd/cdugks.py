@@ -56,7 +56,7 @@ class cdugks_params(ctypes.Structure):
                 ("L_ref", ctypes.c_double), ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
                 ("mu_ref", ctypes.c_double), ("tau", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("dt", ctypes.c_double), ("storage", ctypes.c_int), ("velocity_slices", ctypes.c_int),
-                ("reconstruction", ctypes.c_int)]
+                ("reconstruction", ctypes.c_int), ("face_tile", ctypes.c_int)]
 
 
 _lib = None
@@ -86,6 +86,8 @@ def load_library():
         "cdugks_distributions": (ctypes.c_int, [vp, _DP, _DP]),
         "cdugks_distributions_noalloc": (ctypes.c_int, [vp, _DP, _DP]),
         "cdugks_info": (ctypes.c_int, [vp, _DP, _DP, ctypes.POINTER(i64)]),
+        "cdugks_launch_info": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_int)]),
         "cdugks_storage_info": (ctypes.c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(sz)]),
         "cdugks_profile_phases": (ctypes.c_int, [vp, i64, _DP]),
         "cdugks_destroy": (None, [vp]),
@@ -168,6 +170,7 @@ def describe(prob: dict):
     pa.storage = STORE[prob.get("storage", "f64")]
     pa.reconstruction = RECON[prob.get("reconstruction", "slopes_of_slopes")]
     pa.velocity_slices = int(prob.get("velocity_slices", 0))
+    pa.face_tile = int(prob.get("face_tile", 0))
     return sp, ve, pa
 
 
@@ -291,6 +294,13 @@ class Solver:
         n = ctypes.c_int64()
         check(load_library().cdugks_info(self.ctx, ctypes.byref(dt), ctypes.byref(t), ctypes.byref(n)))
         return dt.value, t.value, n.value
+
+    def launch_info(self):
+        """(face-sum tile shape, 1-based; face-sum velocity slices; update
+        velocity slices)."""
+        t, fs, us = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(load_library().cdugks_launch_info(self.ctx, ctypes.byref(t), ctypes.byref(fs), ctypes.byref(us)))
+        return t.value, fs.value, us.value
 
     def storage_info(self):
         """(velocity rows held in BF16, bytes of one state array)."""

@@ -193,13 +193,16 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
         return fail(CDUGKS_ERR_INVALID, "unknown relax mode %d", pa->relax_mode);
     }
 
-    int t[3];
-    tile_extent(D, t);
+    // face-sum tiles: the default shape plans the velocity split (so the
+    // shape a problem runs with never changes its result)
+    const TileExt t0 = tile_shape(D, 0);
+    const int td[3] = {t0.x, t0.y, t0.z};
     long long nt1 = 1;
     for (int d = 0; d < 3; ++d) {
-        r.tiles1[d] = (r.ne[d] + t[d] - 1) / t[d];
-        nt1 *= r.tiles1[d];
+        r.tiles1_def[d] = (r.ne[d] + td[d] - 1) / td[d];
+        nt1 *= r.tiles1_def[d];
     }
+    set_face_tile(r, 0);
     const long long nt2 = (r.N + 255) / 256;  // update blocks of 256 cells
     // Velocity slices: fill the chip's resident workgroup slots in whole
     // rounds.  The face-sum split fixes the summation order, so it depends only
@@ -234,6 +237,21 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
     // the autotuner may have picked another update split for this class
     // (speed only: the update's result does not depend on it)
     if (int tu = tuned_update_slices(r); tu > 0) r.nslices_upd = (int)std::min<long long>(tu, r.V);
+    // face-sum tile shape: the caller's, else the autotuner's for this
+    // class, else the default (speed only)
+    if (pa->face_tile < 0 || pa->face_tile > tile_shape_count(D))
+        return fail(CDUGKS_ERR_INVALID, "face_tile %d outside 0..%d for dim %d", pa->face_tile,
+                    tile_shape_count(D), D);
+    if (pa->face_tile > 0) {
+        if (!face_tile_usable(r, pa->face_tile - 1))
+            return fail(CDUGKS_ERR_INVALID,
+                        "face_tile %d is not available for this problem (storage form, Dirichlet sides or "
+                        "reconstruction option)",
+                        pa->face_tile);
+        set_face_tile(r, pa->face_tile - 1);
+    } else if (int tt = tuned_face_tile(r); tt > 0 && face_tile_usable(r, tt)) {
+        set_face_tile(r, tt);
+    }
 
     // byte plan
     const size_t es = r.storage == CDUGKS_STORE_F64 ? 8 : 4;
@@ -283,6 +301,26 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
     r.bytes = off;
     *out = r;
     return CDUGKS_OK;
+}
+
+void set_face_tile(Resolved& r, int tile) {
+    const TileExt t = tile_shape(r.D, tile);
+    const int te[3] = {t.x, t.y, t.z};
+    r.tile = tile;
+    for (int d = 0; d < 3; ++d) r.tiles1[d] = (r.ne[d] + te[d] - 1) / te[d];
+}
+
+bool face_tile_usable(const Resolved& r, int tile) {
+    if (tile < 0 || tile >= tile_shape_count(r.D)) return false;
+    if (tile == 0) return true;
+    if (r.any_dirichlet || r.recon != CDUGKS_RECON_SLOPES_OF_SLOPES) return false;
+    if (!face_tile_fits(r.D, tile, r.storage == CDUGKS_STORE_F64 ? 8 : 4)) return false;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+        (void)hipGetLastError();
+        return true;  // no device to ask: the LDS check stands
+    }
+    return face_sum_blocks_per_cu(r.D, r.storage, tile) > 0;
 }
 
 void resident_slots(int D, int storage, long long* R1, long long* R2) {
@@ -441,6 +479,7 @@ void fill_problem(const Resolved& r, char* base, Problem& P) {
     P.err = (int*)(base + r.off_err);
     P.rows = r.storage == CDUGKS_STORE_F32_BF16TAIL ? (const long long*)(base + r.off_rows) : nullptr;
     P.recon = r.recon;
+    P.tile = r.tile;
 }
 
 // Rows of the BF16-tail form: velocity i is a tail row when, for every
@@ -823,6 +862,14 @@ int cdugks_distributions_noalloc(cdugks_ctx* c, double* g, double* b) {
     }
     if (prev >= 0 && prev != c->device) (void)hipSetDevice(prev);
     return rc;
+}
+
+int cdugks_launch_info(cdugks_ctx* c, int* face_tile, int* face_slices, int* update_slices) {
+    if (!c) return fail(CDUGKS_ERR_INVALID, "null context");
+    if (face_tile) *face_tile = c->r.tile + 1;
+    if (face_slices) *face_slices = c->r.nslices;
+    if (update_slices) *update_slices = c->r.nslices_upd;
+    return CDUGKS_OK;
 }
 
 int cdugks_info(cdugks_ctx* c, double* dt, double* t, int64_t* steps) {

@@ -1,0 +1,95 @@
+// Batched face-sum kernels: one persistent launch per class over a device
+// work list that covers every tile of every problem of the class.
+#include "cdugks_device.h"
+
+namespace cdg {
+
+template <typename ST, int MAXD, bool DIR, bool SS>
+__global__ __launch_bounds__(WG) void k_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems,
+                                                          int* queue, int* other) {
+    __shared__ union U {
+        typename FaceSumKernel<1, ST, DIR, SS>::Smem s1;
+        typename FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR, SS>::Smem s2;
+        typename FaceSumKernel<MAXD >= 3 ? 3 : 1, ST, DIR, SS>::Smem s3;
+    } sm;
+    __shared__ int slot;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *other = 0;
+    for (int w = next_item(queue, &slot); w < nitems; w = next_item(queue, &slot)) {
+        const WorkItem it = load_uniform(items + w);
+        const Problem P = load_uniform(probs + it.prob);
+        if (P.D == 1) FaceSumKernel<1, ST, DIR, SS>::run(P, it.tile, it.slice, P.nslices, sm.s1);
+        else if (MAXD >= 2 && P.D == 2)
+            FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR, SS>::run(P, it.tile, it.slice, P.nslices, sm.s2);
+        else if (MAXD >= 3)
+            FaceSumKernel<MAXD >= 3 ? 3 : 1, ST, DIR, SS>::run(P, it.tile, it.slice, P.nslices, sm.s3);
+    }
+}
+
+#define CDG_DISPATCH_MAXD(STORAGE, MAXD, MACRO)                      \
+    do {                                                             \
+        if ((STORAGE) == 0) {                                        \
+            if ((MAXD) == 1) MACRO(double, 1);                       \
+            else if ((MAXD) == 2) MACRO(double, 2);                  \
+            else MACRO(double, 3);                                   \
+        } else if ((STORAGE) == 1) {                                 \
+            if ((MAXD) == 1) MACRO(float, 1);                        \
+            else if ((MAXD) == 2) MACRO(float, 2);                   \
+            else MACRO(float, 3);                                    \
+        } else {                                                     \
+            if ((MAXD) == 1) MACRO(Bf16Tail, 1);                     \
+            else if ((MAXD) == 2) MACRO(Bf16Tail, 2);                \
+            else MACRO(Bf16Tail, 3);                                 \
+        }                                                            \
+    } while (0)
+
+hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int grid,
+                                    int maxd, int storage, bool dirichlet, bool single_slope, int* queue,
+                                    int* other, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+#define CDG_B(DIRV, SSV)                                                                                     \
+    do {                                                                                                     \
+        if ((STORAGE_) == 0) {                                                                               \
+            if (maxd == 1) CDG_LB(double, 1, DIRV, SSV);                                                     \
+            else if (maxd == 2) CDG_LB(double, 2, DIRV, SSV);                                                \
+            else CDG_LB(double, 3, DIRV, SSV);                                                               \
+        } else if ((STORAGE_) == 1) {                                                                        \
+            if (maxd == 1) CDG_LB(float, 1, DIRV, SSV);                                                      \
+            else if (maxd == 2) CDG_LB(float, 2, DIRV, SSV);                                                 \
+            else CDG_LB(float, 3, DIRV, SSV);                                                                \
+        } else {                                                                                             \
+            if (maxd == 1) CDG_LB(Bf16Tail, 1, DIRV, SSV);                                                   \
+            else if (maxd == 2) CDG_LB(Bf16Tail, 2, DIRV, SSV);                                              \
+            else CDG_LB(Bf16Tail, 3, DIRV, SSV);                                                             \
+        }                                                                                                    \
+    } while (0)
+#define CDG_LB(TT, MD, DIRV, SSV)                                                                            \
+    hipLaunchKernelGGL((k_face_sums_batched<TT, MD, DIRV, SSV>), dim3(grid), dim3(WG), 0, s, probs, items,  \
+                       nitems, queue, other)
+#define STORAGE_ storage
+    if (dirichlet) {
+        if (single_slope) CDG_B(true, true);
+        else CDG_B(true, false);
+    } else {
+        if (single_slope) CDG_B(false, true);
+        else CDG_B(false, false);
+    }
+#undef STORAGE_
+#undef CDG_LB
+#undef CDG_B
+    return hipGetLastError();
+}
+
+int batched_face_blocks_per_cu(int maxd, int storage) {
+    int n = 0;
+    hipError_t e = hipSuccess;
+#define CDG_L(TT, MD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums_batched<TT, MD, false, false>), WG, 0)
+    CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
+#undef CDG_L
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return n;
+}
+
+}  // namespace cdg

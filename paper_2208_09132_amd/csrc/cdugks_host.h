@@ -14,7 +14,9 @@ namespace cdg {
 struct Resolved {
     int D;
     int n[3], ne[3], bc[3], nv[3];
-    int tiles1[3];
+    int tiles1[3];      // face-sum tiles per dimension for the chosen shape
+    int tiles1_def[3];  // ... and for the default shape (batched launches, slice plan)
+    int tile;           // face-sum tile shape (index into tile_shape(D, .))
     long long N, NE, V;
     double dx[3];
     double vmin[3], vmax[3];
@@ -51,6 +53,13 @@ long long tail_rows(const Resolved& r, const std::vector<double>& vel, const dou
 void set_pingpong(Problem& P, const Resolved& r, char* base, int cur);
 hipError_t enqueue_step(const Problem& P, hipStream_t s);
 int tuned_update_slices(const Resolved& r);
+int tuned_face_tile(const Resolved& r);
+// Whether face-sum shape `tile` can serve this problem (exists for its
+// dimension, fits the LDS for its storage form, default shape for problems
+// with Dirichlet sides or the single-slope option, and launches on the
+// current device when one is present).
+bool face_tile_usable(const Resolved& r, int tile);
+void set_face_tile(Resolved& r, int tile);
 
 }  // namespace cdg
 

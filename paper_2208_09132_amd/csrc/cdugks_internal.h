@@ -81,6 +81,7 @@ struct Problem {
     // a BF16 row; null otherwise
     const long long* rows;
     int recon;    // 0: slopes of slopes (Sec. 2.1), 1: single slope
+    int tile;     // face-sum tile shape (index into tile_shape(D, .))
 };
 
 // One workgroup's assignment in a batched launch.
@@ -96,6 +97,19 @@ struct WorkItem {
 hipError_t launch_init(const Problem& P, const double* rho, const double* u, const double* T,
                        hipStream_t s);
 hipError_t launch_face_sums(const Problem& P, hipStream_t s);
+// per dimension (one translation unit each)
+hipError_t launch_face_sums_d1(const Problem& P, hipStream_t s);
+hipError_t launch_face_sums_d2(const Problem& P, hipStream_t s);
+hipError_t launch_face_sums_d3(const Problem& P, hipStream_t s);
+// Resident workgroups per CU of the single-problem face-sum kernel of shape
+// `tile` (0 when that shape does not exist for the storage form or no device
+// answers).
+int face_sum_blocks_per_cu(int D, int storage, int tile);
+int face_sum_blocks_per_cu_d1(int storage, int tile);
+int face_sum_blocks_per_cu_d2(int storage, int tile);
+int face_sum_blocks_per_cu_d3(int storage, int tile);
+// Resident workgroups per CU of the batched face-sum kernel of a class.
+int batched_face_blocks_per_cu(int maxd, int storage);
 hipError_t launch_face_close(const Problem& P, hipStream_t s);
 hipError_t launch_cell_close(const Problem& P, hipStream_t s);
 hipError_t launch_update(const Problem& P, hipStream_t s);
@@ -127,12 +141,53 @@ hipError_t launch_cell_close_batched(const Problem* probs, const long long* offs
 // (0 when no device answers).
 int tile_blocks_per_cu(int D, int storage, bool update);
 
-// Tile extents per dimension (256 cells per workgroup); must match the
-// kernels' Tile<D>.
-constexpr void tile_extent(int D, int t[3]) {
-    if (D == 1) { t[0] = 256; t[1] = 1; t[2] = 1; }
-    else if (D == 2) { t[0] = 16; t[1] = 16; t[2] = 1; }
-    else { t[0] = 16; t[1] = 4; t[2] = 4; }
+// Face-sum tile shapes: cells per workgroup along x, y, z, one thread per
+// cell.  Shape 0 of each dimension is the default; the autotuner (or the
+// caller, cdugks_params.face_tile) may choose another for a problem.  A
+// cell's arithmetic does not depend on the tile it sits in (in 2-D every
+// shape keeps its q-box slots in registers, see Geo), and the velocity split
+// is planned with the default shape, so every shape gives bitwise the same
+// result.  Shapes wider along x use more of each 128-byte line of a halo row;
+// shapes of 768 cells stage larger boxes per workgroup (less halo per cell).
+struct TileExt {
+    int x, y, z;
+};
+constexpr int MAX_TILE_SHAPES = 6;
+constexpr int tile_shape_count(int D) { return D == 1 ? 1 : (D == 2 ? 4 : 6); }
+constexpr TileExt tile_shape(int D, int id) {
+    if (D == 1) return TileExt{256, 1, 1};
+    if (D == 2) {
+        switch (id) {
+        case 1: return TileExt{32, 8, 1};
+        case 2: return TileExt{8, 32, 1};
+        case 3: return TileExt{32, 24, 1};
+        default: return TileExt{16, 16, 1};
+        }
+    }
+    switch (id) {
+    case 1: return TileExt{32, 4, 2};
+    case 2: return TileExt{64, 2, 2};
+    case 3: return TileExt{32, 6, 4};
+    case 4: return TileExt{64, 4, 3};
+    case 5: return TileExt{16, 8, 6};
+    default: return TileExt{16, 4, 4};
+    }
 }
+constexpr int tile_threads(int D, int id) {
+    return tile_shape(D, id).x * tile_shape(D, id).y * tile_shape(D, id).z;
+}
+// Static LDS of a face-sum workgroup (element size es of the stencil
+// arithmetic): q box and limited-difference box for g and b, double-buffered
+// in 1-D and 2-D.  Shapes whose boxes exceed the 160 KB of a CU do not exist
+// for that storage form.
+constexpr long long face_sum_lds_bytes(int D, int id, int es) {
+    const TileExt t = tile_shape(D, id);
+    const long long qx = t.x + 5, qy = D >= 2 ? t.y + 5 : 1, qz = D >= 3 ? t.z + 5 : 1;
+    const long long ax = t.x + 3, ay = D >= 2 ? t.y + 3 : 1, az = D >= 3 ? t.z + 3 : 1;
+    const long long nbuf = D <= 2 ? 2 : 1;
+    return nbuf * 2 * es * (qx * qy * qz + D * ax * ay * az);
+}
+constexpr long long LDS_PER_CU = 160 * 1024;
+constexpr bool face_tile_fits(int D, int id, int es) { return face_sum_lds_bytes(D, id, es) <= LDS_PER_CU; }
 
 }  // namespace cdg

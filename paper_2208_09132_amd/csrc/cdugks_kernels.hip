@@ -30,280 +30,9 @@
 // of phi_bar_plus and of the limited slopes are staged in LDS.  The face
 // values phi_bar (velocity-major [d][g|b][V][NE]) are written once and read
 // by the update, which therefore needs no stencil and no halo.
-#include "cdugks_internal.h"
-
-#include <math.h>
-
-#include <type_traits>
+#include "cdugks_device.h"
 
 namespace cdg {
-
-constexpr int WG = 256;
-
-__device__ __forceinline__ int map_coord(int x, int n, int bc) {
-    if (bc == 0) {
-        int r = x % n;
-        return r < 0 ? r + n : r;
-    }
-    return x < 0 ? 0 : (x >= n ? n - 1 : x);
-}
-
-// Reciprocal from the hardware estimate (relative error below 1e-7) refined
-// by one Newton-Raphson step, which squares the error to about 2e-15.  Used
-// where the operand is a nonzero finite sum.
-__device__ __forceinline__ double rcp_nr(double s) {
-    const double r = __builtin_amdgcn_rcp(s);
-    return fma(r, fma(-s, r, 1.0), r);
-}
-
-// Van Leer limiter (eq. VanLeer) at half scale: H(a, b) = ab/(a + b) when
-// ab > 0, else 0, which is half the harmonic-mean form 2ab/(a+b) =
-// (sgn a + sgn b)|a||b|/(|a|+|b|): zero at extrema and for a flat side.  The
-// kernels carry every limited slope at half scale (and slopes of slopes at a
-// quarter), folding the factors into the Courant numbers; all the scalings
-// are powers of two, so the values are those of the full-scale form exactly
-// (except where a product is subnormal, as in the far velocity tails of the
-// FP32 form).
-// When ab > 0 the sum a + b is nonzero, so the reciprocal is safe; otherwise
-// its value is discarded by the select.
-__device__ __forceinline__ double half_van_leer(double a, double b) {
-    double p = a * b;
-    double v = p * rcp_nr(a + b);
-    return p > 0.0 ? v : 0.0;
-}
-
-// FP32 form for the FP32-storage stencil: the hardware reciprocal alone
-// (within 1 ulp), so the limited slope is within about 2 ulp of the rounded
-// quotient, below the rounding of the FP32 values it is built from and
-// stored as.
-__device__ __forceinline__ float half_van_leer(float a, float b) {
-    float p = a * b;
-    float v = p * __builtin_amdgcn_rcpf(a + b);
-    return p > 0.0f ? v : 0.0f;
-}
-
-template <typename ST>
-__device__ __forceinline__ double ld(const void* base, long long idx) {
-    return (double)reinterpret_cast<const ST*>(base)[idx];
-}
-template <typename ST>
-__device__ __forceinline__ void st(void* base, long long idx, double v) {
-    reinterpret_cast<ST*>(base)[idx] = (ST)v;
-}
-
-// Streaming store for data the writing kernel never reads again (face values,
-// the new distributions): marked non-temporal so it does not push the halo
-// lines that neighbouring workgroups still need out of L2.
-template <typename ST>
-__device__ __forceinline__ void st_stream(void* base, long long idx, double v) {
-    __builtin_nontemporal_store((ST)v, reinterpret_cast<ST*>(base) + idx);
-}
-
-__device__ __forceinline__ void raise_error(int* err) { *err = 1; }
-
-// ---------------------------------------------------------------------------
-// storage forms of the distributions g, b (and of the 3-D quarter-step fields)
-// ---------------------------------------------------------------------------
-// double, float: every velocity row [N] in that precision.
-// Bf16Tail: the FP32 form, except that the rows of the far velocity tails
-// (fixed at set-up) hold BF16.  P.rows[i] is the byte offset of row i inside
-// each state array, with bit 0 set for a BF16 row.  The stencil arithmetic
-// and the stored face values are FP32 as in the FP32 form.  Values are
-// rounded to FP32 and then, in a BF16 row, to BF16 (round to nearest even).
-struct Bf16Tail {};
-
-template <typename ST>
-struct StoreT {
-    using C = ST;  // stencil arithmetic and stored face values
-    using R = ST;  // a loaded state value, as held in registers until used
-    static constexpr bool MIXED = false;
-};
-template <>
-struct StoreT<Bf16Tail> {
-    using C = float;
-    using R = unsigned;  // raw bits: the FP32 word, or the BF16 half zero-extended
-    static constexpr bool MIXED = true;
-};
-
-// row word of velocity i (uniform: a scalar load)
-__device__ __forceinline__ long long row_word(const Problem& P, int i) {
-    return ((const __attribute__((address_space(4))) long long*)(const void*)P.rows)[i];
-}
-
-// state value at (velocity i, cell c), raw until state_value converts it
-template <typename ST>
-__device__ __forceinline__ typename StoreT<ST>::R state_load(const Problem& P, const void* base, int i,
-                                                            long long c) {
-    if constexpr (StoreT<ST>::MIXED) {
-        const long long o = row_word(P, i);
-        const char* row = (const char*)base + (o & ~1LL);
-        if (o & 1) return (unsigned)((const unsigned short*)row)[c];
-        return ((const unsigned*)row)[c];
-    } else {
-        return ((const ST*)base)[(long long)i * P.pitch + c];
-    }
-}
-template <typename ST>
-__device__ __forceinline__ double state_value(const Problem& P, int i, typename StoreT<ST>::R r) {
-    if constexpr (StoreT<ST>::MIXED) {
-        return (double)__uint_as_float((row_word(P, i) & 1) ? r << 16 : r);
-    } else {
-        return (double)r;
-    }
-}
-template <typename ST>
-__device__ __forceinline__ double state_ld(const Problem& P, const void* base, int i, long long c) {
-    return state_value<ST>(P, i, state_load<ST>(P, base, i, c));
-}
-template <typename ST, bool STREAM>
-__device__ __forceinline__ void state_st(const Problem& P, void* base, int i, long long c, double v) {
-    if constexpr (StoreT<ST>::MIXED) {
-        const long long o = row_word(P, i);
-        char* row = (char*)base + (o & ~1LL);
-        const float f = (float)v;
-        if (o & 1) {
-            const unsigned short h = __builtin_bit_cast(unsigned short, (__bf16)f);
-            if constexpr (STREAM) __builtin_nontemporal_store(h, (unsigned short*)row + c);
-            else ((unsigned short*)row)[c] = h;
-        } else {
-            if constexpr (STREAM) __builtin_nontemporal_store(f, (float*)row + c);
-            else ((float*)row)[c] = f;
-        }
-    } else {
-        if constexpr (STREAM) st_stream<ST>(base, (long long)i * P.pitch + c, v);
-        else st<ST>(base, (long long)i * P.pitch + c, v);
-    }
-}
-
-// The fields of velocity i at NS source cells of one thread, with a single
-// format branch per velocity (the row kind is uniform); raw until slot_value.
-template <typename ST, int NS>
-__device__ __forceinline__ void load_slots(const Problem& P, const void* sg, const void* sb, int i,
-                                           const long long (&src)[NS], typename StoreT<ST>::R (&og)[NS],
-                                           typename StoreT<ST>::R (&ob)[NS]) {
-    if constexpr (StoreT<ST>::MIXED) {
-        const long long o = row_word(P, i);
-        const char* rg = (const char*)sg + (o & ~1LL);
-        const char* rb = (const char*)sb + (o & ~1LL);
-        if (o & 1) {
-#pragma unroll
-            for (int k = 0; k < NS; ++k) {
-                og[k] = ((const unsigned short*)rg)[src[k]];
-                ob[k] = ((const unsigned short*)rb)[src[k]];
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < NS; ++k) {
-                og[k] = ((const unsigned*)rg)[src[k]];
-                ob[k] = ((const unsigned*)rb)[src[k]];
-            }
-        }
-    } else {
-        // the row's base address is uniform (scalar) and the cell offsets
-        // are loop-invariant, so each load is a scalar base plus a fixed
-        // vector offset
-        const ST* const rg = (const ST*)sg + (long long)i * P.pitch;
-        const ST* const rb = (const ST*)sb + (long long)i * P.pitch;
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-            og[k] = rg[src[k]];
-            ob[k] = rb[src[k]];
-        }
-    }
-}
-// value of a raw slot; shift = 16 for a BF16 row, else 0 (uniform)
-template <typename ST>
-__device__ __forceinline__ double slot_value(typename StoreT<ST>::R r, unsigned shift) {
-    if constexpr (StoreT<ST>::MIXED) return (double)__uint_as_float(r << shift);
-    else return (double)r;
-}
-
-// Access within one velocity row whose kind is known at compile time: `off`
-// is the element offset i N of the row (double, float) or its byte offset
-// (Bf16Tail, H: the row holds BF16).
-template <typename ST, bool H>
-__device__ __forceinline__ double row_ld(const void* base, long long off, long long c) {
-    if constexpr (StoreT<ST>::MIXED) {
-        const char* row = (const char*)base + off;
-        if constexpr (H) return (double)(float)((const __bf16*)row)[c];
-        else return (double)((const float*)row)[c];
-    } else {
-        return (double)((const ST*)base)[off + c];
-    }
-}
-template <typename ST, bool H>
-__device__ __forceinline__ double row_round(double v) {
-    if constexpr (StoreT<ST>::MIXED) {
-        if constexpr (H) return (double)(float)(__bf16)(float)v;
-        else return (double)(float)v;
-    } else {
-        return (double)(ST)v;
-    }
-}
-template <typename ST, bool H>
-__device__ __forceinline__ void row_st_stream(void* base, long long off, long long c, double v) {
-    if constexpr (StoreT<ST>::MIXED) {
-        char* row = (char*)base + off;
-        if constexpr (H) {
-            const unsigned short h = __builtin_bit_cast(unsigned short, (__bf16)(float)v);
-            __builtin_nontemporal_store(h, (unsigned short*)row + c);
-        } else {
-            __builtin_nontemporal_store((float)v, (float*)row + c);
-        }
-    } else {
-        st_stream<ST>(base, off + c, v);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// primitives shared by the per-cell and per-face closures (Sec. 2)
-// ---------------------------------------------------------------------------
-struct Prim {
-    double rho, u[3], RT, inv_tau_g;
-    bool bad;
-};
-
-__device__ Prim primitives(const Problem& P, const double* Wv) {
-    Prim q;
-    const int D = P.D;
-    q.rho = Wv[0];
-    double u2 = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        q.u[d] = d < D ? Wv[1 + d] / q.rho : 0.0;
-        u2 += q.u[d] * q.u[d];
-    }
-    double E = Wv[D + 1] / q.rho;
-    double T = (P.gamma - 1.0) / P.R * (E - 0.5 * u2);
-    q.RT = P.R * T;
-    if (P.relax == 0) {
-        double mu = P.mu_ref * pow(T / P.T_ref, P.omega);
-        q.inv_tau_g = q.rho * q.RT / mu;
-    } else {
-        q.inv_tau_g = P.tau_inv;
-    }
-    q.bad = !(q.rho > 0.0) || !(T > 0.0) || !isfinite(q.rho) || !isfinite(T) ||
-            !isfinite(q.u[0]) || !isfinite(q.u[1]) || !isfinite(q.u[2]) || !isfinite(q.inv_tau_g);
-    return q;
-}
-
-__device__ __forceinline__ double maxwell_prefactor(const Problem& P, double rho, double RT) {
-    double two_pi_rt = 2.0 * M_PI * RT;
-    double f = P.D == 1 ? 1.0 / sqrt(two_pi_rt)
-                        : (P.D == 2 ? 1.0 / two_pi_rt : 1.0 / (two_pi_rt * sqrt(two_pi_rt)));
-    return rho * f;
-}
-
-__device__ void write_cell_coefs(const Problem& P, double* Pc, long long N, long long c, const Prim& q) {
-    double beta = 0.25 * P.dt * q.inv_tau_g;
-    Pc[PC_A * N + c] = maxwell_prefactor(P, q.rho, q.RT);
-    Pc[PC_INV2RT * N + c] = 0.5 / q.RT;
-    Pc[PC_CRT2 * N + c] = 0.5 * P.c_int * q.RT;
-    Pc[PC_BETA * N + c] = beta;
-    Pc[PC_BETAB * N + c] = beta * P.Pr;
-    Pc[PC_ETA * N + c] = beta * (P.Pr - 1.0);
-    Pc[PC_HU2 * N + c] = 0.5 * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]);
-    for (int d = 0; d < 3; ++d) Pc[(PC_U0 + d) * N + c] = q.u[d];
-}
 
 // ---------------------------------------------------------------------------
 // init: W^0 from (rho, u, T) and the cell coefficients; then phi^0 = phi_eq
@@ -349,129 +78,7 @@ __global__ __launch_bounds__(WG) void k_init_phi(Problem P) {
     state_st<ST, false>(P, const_cast<void*>(P.b_in), (int)i, c, beq);
 }
 
-// ---------------------------------------------------------------------------
-// tile kernels
-// ---------------------------------------------------------------------------
-template <int D> struct Tile;
-template <> struct Tile<1> { static constexpr int X = 256, Y = 1, Z = 1; };
-template <> struct Tile<2> { static constexpr int X = 16, Y = 16, Z = 1; };
-// 3-D: 16 cells along x, so that a row of the q box (21 cells) spans whole
-// 128-byte lines in FP32 (an 8-wide tile fetched 17x the field bytes of the
-// 3-D FP32 face sums from HBM; 16 x 4 x 4 halves the kernel's time).  Must
-// match tile_extent on the host.
-template <> struct Tile<3> { static constexpr int X = 16, Y = 4, Z = 4; };
 
-template <int D>
-constexpr bool tile_matches_host() {
-    int t[3] = {0, 0, 0};
-    tile_extent(D, t);
-    return t[0] == Tile<D>::X && t[1] == Tile<D>::Y && t[2] == Tile<D>::Z;
-}
-static_assert(tile_matches_host<1>() && tile_matches_host<2>() && tile_matches_host<3>(),
-              "the host's tile_extent and the kernels' Tile<D> differ");
-
-// XCD-aware order: consecutive workgroup ids are spread over the 8 XCDs, so
-// give each XCD a contiguous block of the (tile, slice) space; neighbouring
-// tiles then share halo lines in that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int lin, int total) {
-    int per = total / 8;
-    if (lin >= per * 8) return lin;
-    return (lin % 8) * per + lin / 8;
-}
-
-// Box geometry of the staged halo for a face-sum tile: the q box covers tile
-// offsets [-3, T+1], the limited-difference box [-2, T].  (The left face of
-// cell c along d needs the upwind cell c-d or c, its slopes at the upwind
-// cell +-1 along d, and those need q one further out.)
-template <int D>
-struct Geo {
-    static constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
-    static constexpr int QX = TX + 5;
-    static constexpr int QY = D >= 2 ? TY + 5 : 1;
-    static constexpr int QZ = D >= 3 ? TZ + 5 : 1;
-    static constexpr int AX = TX + 3;
-    static constexpr int AY = D >= 2 ? TY + 3 : 1;
-    static constexpr int AZ = D >= 3 ? TZ + 3 : 1;
-    static constexpr int NQ = QX * QY * QZ;
-    static constexpr int NA = AX * AY * AZ;
-    static constexpr int NRA = (NA + WG - 1) / WG;   // slope points per thread
-    static constexpr bool CACHE_COEF = (NQ - TX * TY * TZ + WG - 1) / WG + 1 <= 2;
-    // offsets of tile coordinate 0 inside the boxes, and box strides
-    static constexpr int OQX = 3, OQY = D >= 2 ? 3 : 0, OQZ = D >= 3 ? 3 : 0;
-    static constexpr int OAX = 2, OAY = D >= 2 ? 2 : 0, OAZ = D >= 3 ? 2 : 0;
-    __device__ static constexpr int SQ(int e) { return e == 0 ? 1 : (e == 1 ? QX : QX * QY); }
-    __device__ static constexpr int SA(int e) { return e == 0 ? 1 : (e == 1 ? AX : AX * AY); }
-    __device__ static int qidx(int x, int y, int z) { return (x + OQX) + QX * ((y + OQY) + QY * (z + OQZ)); }
-    __device__ static int aidx(int x, int y, int z) { return (x + OAX) + AX * ((y + OAY) + AY * (z + OAZ)); }
-};
-
-struct CellCoef {
-    double A, inv2RT, cRT2, beta, betab, eta, hu2, u[3];
-};
-
-__device__ __forceinline__ CellCoef load_coef(const double* Pc, long long N, long long c) {
-    CellCoef k;
-    k.A = Pc[PC_A * N + c];
-    k.inv2RT = Pc[PC_INV2RT * N + c];
-    k.cRT2 = Pc[PC_CRT2 * N + c];
-    k.beta = Pc[PC_BETA * N + c];
-    k.betab = Pc[PC_BETAB * N + c];
-    k.eta = Pc[PC_ETA * N + c];
-    k.hu2 = Pc[PC_HU2 * N + c];
-    k.u[0] = Pc[PC_U0 * N + c];
-    k.u[1] = Pc[(PC_U0 + 1) * N + c];
-    k.u[2] = Pc[(PC_U0 + 2) * N + c];
-    return k;
-}
-
-struct Vel {
-    double xi[3], w, hx2, lam2[3];
-};
-
-// The velocity table is read-only for the whole launch: reading it through the
-// constant address space makes the per-velocity loads scalar (SMEM), so they
-// neither occupy vector-memory slots nor delay waits on the field loads.
-typedef const __attribute__((address_space(4))) double* const_dptr;
-
-__device__ __forceinline__ const_dptr vel_ptr(const double* vel, int i) {
-    return (const_dptr)(const void*)(vel + (long long)i * NVEL);
-}
-
-__device__ __forceinline__ Vel load_vel(const double* vel, int i) {
-    const_dptr v = vel_ptr(vel, i);
-    Vel r;
-    r.xi[0] = v[0]; r.xi[1] = v[1]; r.xi[2] = v[2];
-    r.w = v[VE_W]; r.hx2 = v[VE_HX2];
-    r.lam2[0] = v[VE_LAM0]; r.lam2[1] = v[VE_LAM0 + 1]; r.lam2[2] = v[VE_LAM0 + 2];
-    return r;
-}
-
-// Z and the quarter-step fields at one (cell, velocity), given g_eq:
-// phi_bar_plus = phi + (h/2)(phi_eq - phi)/tau + (h/2) S, S_b = Z (g - g_eq)/tau_bg.
-template <int D>
-__device__ __forceinline__ void quarter_step_eq(const CellCoef& k, const Vel& v, double geq, double g, double b,
-                                                double& qg, double& qb) {
-    double xu = 0.0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) xu += v.xi[d] * k.u[d];
-    double beq = (v.hx2 + k.cRT2) * geq;
-    double Z = xu - k.hu2;
-    qg = g + k.beta * (geq - g);
-    qb = b + k.betab * (beq - b) + k.eta * Z * (g - geq);
-}
-
-// The same with the equilibrium evaluated directly.
-template <int D>
-__device__ __forceinline__ void quarter_step(const CellCoef& k, const Vel& v, double g, double b, double& qg,
-                                             double& qb) {
-    double c2 = 0.0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        double x = v.xi[d] - k.u[d];
-        c2 += x * x;
-    }
-    quarter_step_eq<D>(k, v, k.A * exp(-c2 * k.inv2RT), g, b, qg, qb);
-}
 
 // Quarter-step fields of the initial state (when they are stored): the same
 // arithmetic the update kernel applies to each new state.
@@ -496,844 +103,7 @@ __global__ __launch_bounds__(256) void k_init_quarter(Problem P) {
     state_st<ST, false>(P, P.qb, (int)i, c, qb);
 }
 
-// Value of phi_bar at a face centre at t_{n+1/2} from the upwind cell u,
-// side s = +1 when the face is u's right face, -1 when its left face:
-//   v = q(u) + s a_d/2 - sum_e lambda_e (a_e + s b_de/2),
-// a_e = VL of one-sided differences of q along e (slope times dx_e) and
-// b_de = VL of differences of a_e along d (slope of the slope times dx_d dx_e).
-// Arguments at the scales the kernels carry: ha = a/2 at u (haU) and at
-// u - d (haL), u + d (haR); lam2 = 2 lambda.  Then
-//   v = q(u) + s ha_d - sum_e lam2_e (ha_e + s hb_de),  hb_de = b_de/4 = H(ha differences).
-template <int D, typename CT>
-__device__ __forceinline__ CT face_value_at(CT qU, const CT* haU, const CT* haL, const CT* haR, int d, CT s,
-                                            const Vel& v) {
-    CT val = qU + s * haU[d];
-#pragma unroll
-    for (int e = 0; e < D; ++e) {
-        CT hb = half_van_leer(haU[e] - haL[e], haR[e] - haU[e]);
-        val -= CT(v.lam2[e]) * (haU[e] + s * hb);
-    }
-    return val;
-}
 
-// The single-slope option: the upwind cell's own slopes carried to the foot,
-// v = q(u) + s ha_d - sum_e lam2_e ha_e (no slopes of slopes).
-template <int D, typename CT>
-__device__ __forceinline__ CT face_value_single(CT qU, const CT* haU, int d, CT s, const Vel& v) {
-    CT val = qU + s * haU[d];
-#pragma unroll
-    for (int e = 0; e < D; ++e) val -= CT(v.lam2[e]) * haU[e];
-    return val;
-}
-
-// Face coefficients used to invert eq. phibar at a face: NFC per face.
-template <int D>
-struct FaceCoef {
-    static constexpr int NFC = 9 + D;
-    double A, inv2RT, cRT2, ig, bg, ib, bb, eb, hu2, u[D];
-    __device__ void load(const double* F, long long NE) {
-        A = F[PF_A * NE];
-        inv2RT = F[PF_INV2RT * NE];
-        cRT2 = F[PF_CRT2 * NE];
-        ig = F[PF_IG * NE];
-        bg = F[PF_BG * NE];
-        ib = F[PF_IB * NE];
-        bb = F[PF_BB * NE];
-        eb = F[PF_EB * NE];
-        hu2 = F[PF_HU2 * NE];
-#pragma unroll
-        for (int e = 0; e < D; ++e) u[e] = F[(PF_U0 + e) * NE];
-    }
-    // LDS layout [NFC][stride]
-    __device__ void store(double* s, int j, int stride) const {
-        s[0 * stride + j] = A; s[1 * stride + j] = inv2RT; s[2 * stride + j] = cRT2;
-        s[3 * stride + j] = ig; s[4 * stride + j] = bg; s[5 * stride + j] = ib;
-        s[6 * stride + j] = bb; s[7 * stride + j] = eb; s[8 * stride + j] = hu2;
-#pragma unroll
-        for (int e = 0; e < D; ++e) s[(9 + e) * stride + j] = u[e];
-    }
-    __device__ void fetch(const double* s, int j, int stride) {
-        A = s[0 * stride + j]; inv2RT = s[1 * stride + j]; cRT2 = s[2 * stride + j];
-        ig = s[3 * stride + j]; bg = s[4 * stride + j]; ib = s[5 * stride + j];
-        bb = s[6 * stride + j]; eb = s[7 * stride + j]; hu2 = s[8 * stride + j];
-#pragma unroll
-        for (int e = 0; e < D; ++e) u[e] = s[(9 + e) * stride + j];
-    }
-    // phi at the face from phi_bar: g = ig gbar + bg g_eq; b likewise with the
-    // S_b source at the face evaluated with the face g.
-
-    __device__ __forceinline__ void invert(const Vel& v, double geq, double vg, double vb, double& gF,
-                                           double& bF) const {
-        double xu = 0.0;
-#pragma unroll
-        for (int e = 0; e < D; ++e) xu += v.xi[e] * u[e];
-        double beq = (v.hx2 + cRT2) * geq;
-        double Z = xu - hu2;
-        gF = ig * vg + bg * geq;
-        bF = ib * vb + bb * beq + eb * Z * (gF - geq);
-    }
-};
-
-// ---------------------------------------------------------------------------
-// Maxwellian by recurrence along the fastest velocity axis.  The nodes of
-// velocity axis 0 are uniform (spacing h); with x_k = xi_k - u_x, s = 1/(2RT)
-// and everything else fixed,
-//   g_eq(k+1) = g_eq(k) R_k,  R_k = exp(-(2 x_k + h) h s),  R_{k+1} = R_k C,
-//   C = exp(-2 h^2 s).
-// g_eq and R are set from direct exponentials at every WALK-th node of axis 0
-// (anchors; a row of the velocity grid starts with one), which bounds the
-// rounding drift of the products to about WALK^2 ulp.  A block whose
-// exponents could leave the range where the products stay normal numbers
-// uses direct exponentials throughout.  The value at a node depends only on
-// the node, not on where a velocity slice starts: a slice starting inside a
-// block walks from that block's anchor.
-// ---------------------------------------------------------------------------
-constexpr int WALK = 8;
-
-template <int D>
-__device__ __forceinline__ double maxwellian(double A, double s, const double* u, const Vel& v) {
-    double c2 = 0.0;
-#pragma unroll
-    for (int e = 0; e < D; ++e) {
-        const double x = v.xi[e] - u[e];
-        c2 += x * x;
-    }
-    return A * exp(-c2 * s);
-}
-
-struct GaussWalk {
-    double E, R, C;
-    bool ok;
-    __device__ __forceinline__ void init(double s, double h) { C = exp(-2.0 * h * h * s); }
-    // anchor at the current node (its axis-0 coordinate is v.xi[0])
-    template <int D>
-    __device__ __forceinline__ void anchor(double A, double s, const double* u, const Vel& v, double h) {
-        const double x = v.xi[0] - u[0];
-        E = maxwellian<D>(A, s, u, v);
-        R = exp(-(x + x + h) * h * s);
-        const double m = fmax(fabs(x), fabs(x + (WALK - 1) * h));
-        ok = m * m * s < 600.0 && (m + m + h) * h * s < 600.0 && h * h * s < 300.0;
-    }
-    __device__ __forceinline__ void advance() {
-        E *= R;
-        R *= C;
-    }
-    template <int D>
-    __device__ __forceinline__ double value(double A, double s, const double* u, const Vel& v) const {
-        double geq = E;
-        if (!ok) geq = maxwellian<D>(A, s, u, v);
-        return geq;
-    }
-};
-
-// ---------------------------------------------------------------------------
-// face-sum kernel: for every velocity of the slice, phi_bar at the left face
-// of each tile cell along each d (stored for the update kernel), and the
-// velocity sums of the face (serial per thread, fixed order)
-// ---------------------------------------------------------------------------
-// DIR: the problem has Dirichlet sides; their ghost slots of the q box take
-// the fixed states' equilibria (a separate instantiation keeps the register
-// budget of the others unchanged).
-// SS: the single-slope reconstruction option (stage 3 reads only the upwind
-// cell's slopes).
-template <int D, typename ST, bool DIR = false, bool SS = false>
-struct FaceSumKernel {
-    using G = Geo<D>;
-    // stencil arithmetic (quarter-step values in LDS, limiters, face values) in
-    // the storage precision; equilibria and the velocity sums stay FP64
-    using CT = typename StoreT<ST>::C;
-    using RT = typename StoreT<ST>::R;
-    static constexpr int NT = G::TX * G::TY * G::TZ;
-    // q-box points per thread: slot 0 is the thread's own cell, the other
-    // slots cover the halo
-    static constexpr int NHALO = G::NQ - NT;
-    static constexpr int NSLOT = 1 + (NHALO + WG - 1) / WG;
-
-    // Box index of the h-th point of a box (extents BX, BY, BZ; the tile sits
-    // at offsets OX, OY, OZ) that lies outside the tile, in box order: planes
-    // below the tile in z are full, the tile's planes miss its TX x TY block,
-    // and likewise rows within a plane.
-    template <int BX, int BY, int OX, int OY, int OZ>
-    __device__ static int ring_point(int h) {
-        constexpr int PL = BX * BY;                 // points per full plane
-        constexpr int PI = PL - G::TX * G::TY;      // ring points per tile plane
-        constexpr int RI = BX - G::TX;              // ring points per tile row
-        if (h < OZ * PL) return h;  // below the tile: box order equals ring order
-        h -= OZ * PL;
-        if (h >= G::TZ * PI) return (OZ + G::TZ) * PL + (h - G::TZ * PI);  // above
-        const int z = OZ + h / PI;
-        int rem = h % PI, y, x;
-        if (rem < OY * BX) {
-            y = rem / BX;
-            x = rem % BX;
-        } else {
-            rem -= OY * BX;
-            if (rem >= G::TY * RI) {
-                rem -= G::TY * RI;
-                y = OY + G::TY + rem / BX;
-                x = rem % BX;
-            } else {
-                y = OY + rem / RI;
-                const int c = rem % RI;
-                x = c < OX ? c : c + G::TX;
-            }
-        }
-        return x + BX * (y + BY * z);
-    }
-    __device__ static int halo_point(int h) { return ring_point<G::QX, G::QY, G::OQX, G::OQY, G::OQZ>(h); }
-    __device__ static int slope_ring_point(int h) {
-        return ring_point<G::AX, G::AY, G::OAX, G::OAY, G::OAZ>(h);
-    }
-    // slope-box points outside the tile, and passes over them
-    static constexpr int NARING = G::NA - NT;
-    static constexpr int NRING2 = (2 * NARING + WG - 1) / WG;  // (point, field) passes
-
-    // when the q-box points do not fit in registers, the cell coefficients
-    // of the whole box are staged in LDS once (3-D FP32; the FP64 3-D box does
-    // not fit and reads them from memory)
-    // With stored quarter-step fields the q box is loaded, not computed.
-    static constexpr bool QS = quarter_stored(D);
-    // cell coefficients of the q-box slots in registers
-    static constexpr bool KQ = G::CACHE_COEF && !QS;
-    static constexpr bool COEF_LDS = !G::CACHE_COEF && sizeof(CT) == 4 && !QS;
-
-    // 1-D and 2-D alternate two LDS buffers between consecutive velocities,
-    // which removes the barrier that would otherwise end each velocity
-    static constexpr int NBUF = D <= 2 ? 2 : 1;
-
-    struct Smem {
-        CT q[NBUF][2][G::NQ];      // phi_bar_plus for g, b
-        CT a[NBUF][2][D * G::NA];  // limited differences for g, b
-        double kc[COEF_LDS ? 10 * G::NQ : 1];  // [coefficient][box point]
-    };
-
-    __device__ static void run(const Problem& P, int tile, int slice, int nslices, Smem& sm) {
-        const int tid = threadIdx.x;
-        const long long N = P.N;
-        int t = tile;
-        const int ox = (t % P.tiles1[0]) * G::TX;
-        t /= P.tiles1[0];
-        const int oy = D >= 2 ? (t % P.tiles1[1]) * G::TY : 0;
-        t /= P.tiles1[1];
-        const int oz = D >= 3 ? t * G::TZ : 0;
-        const int v0 = (int)((long long)P.V * slice / nslices);
-        const int v1 = (int)((long long)P.V * (slice + 1) / nslices);
-
-        // q-box points of this thread: slot 0 its own cell, then halo points
-        // (halo enumerated in box order, interior skipped); source cell after
-        // periodic wrap / outflow clamp
-        // lq: box index in the low 20 bits; for a Dirichlet ghost, its side
-        // 2 d + side plus one in the bits above (-1: unused slot)
-        long long srcq[NSLOT];
-        int lq[NSLOT];
-        CellCoef kq[KQ ? NSLOT : 1];
-        {
-            int lx = tid % G::TX, ly = (tid / G::TX) % G::TY, lz = tid / (G::TX * G::TY);
-            lq[0] = G::qidx(lx, ly, lz);
-#pragma unroll
-            for (int k = 1; k < NSLOT; ++k) {
-                const int h = tid + (k - 1) * WG;  // halo ordinal
-                lq[k] = h < NHALO ? halo_point(h) : -1;
-            }
-#pragma unroll
-            for (int k = 0; k < NSLOT; ++k) {
-                srcq[k] = 0;  // unused slots still load a valid address
-                if (lq[k] < 0) continue;
-                int r = lq[k];
-                int rx = r % G::QX, ry = (r / G::QX) % G::QY, rz = r / (G::QX * G::QY);
-                const int c3[3] = {ox + rx - G::OQX, oy + ry - G::OQY, oz + rz - G::OQZ};
-                if constexpr (DIR) {
-                    int side = 0;
-#pragma unroll
-                    for (int d = 0; d < D; ++d)
-                        if (P.bc[d] == 2 && (c3[d] < 0 || c3[d] >= P.n[d])) side = 2 * d + (c3[d] >= P.n[d]) + 1;
-                    lq[k] = r | (side << 20);
-                }
-                int cx = map_coord(c3[0], P.n[0], P.bc[0]);
-                int cy = D >= 2 ? map_coord(c3[1], P.n[1], P.bc[1]) : 0;
-                int cz = D >= 3 ? map_coord(c3[2], P.n[2], P.bc[2]) : 0;
-                srcq[k] = cx + (long long)P.n[0] * (cy + (long long)P.n[1] * cz);
-                if constexpr (KQ) kq[k] = load_coef(P.P_in, N, srcq[k]);
-            }
-        }
-        if constexpr (COEF_LDS) {
-            for (int r = tid; r < G::NQ; r += WG) {
-                int rx = r % G::QX, ry = (r / G::QX) % G::QY, rz = r / (G::QX * G::QY);
-                int cx = map_coord(ox + rx - G::OQX, P.n[0], P.bc[0]);
-                int cy = D >= 2 ? map_coord(oy + ry - G::OQY, P.n[1], P.bc[1]) : 0;
-                int cz = D >= 3 ? map_coord(oz + rz - G::OQZ, P.n[2], P.bc[2]) : 0;
-                const CellCoef k = load_coef(P.P_in, N, cx + (long long)P.n[0] * (cy + (long long)P.n[1] * cz));
-                double* o = sm.kc + r;
-                o[0 * G::NQ] = k.A; o[1 * G::NQ] = k.inv2RT; o[2 * G::NQ] = k.cRT2; o[3 * G::NQ] = k.beta;
-                o[4 * G::NQ] = k.betab; o[5 * G::NQ] = k.eta; o[6 * G::NQ] = k.hu2;
-                o[7 * G::NQ] = k.u[0]; o[8 * G::NQ] = k.u[1]; o[9 * G::NQ] = k.u[2];
-            }
-            __syncthreads();
-        }
-
-        // own cell = the left faces this thread reconstructs
-        const int tx = tid % G::TX, ty = (tid / G::TX) % G::TY, tz = tid / (G::TX * G::TY);
-        const int gx = ox + tx, gy = oy + ty, gz = oz + tz;
-        const long long NE = P.NE;
-        long long fe = -1;  // extended-grid index of the own cell's left faces
-        bool fvalid[D];
-        {
-            int cc[3] = {gx, gy, gz};
-            bool any = false;
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                bool ok = true;
-#pragma unroll
-                for (int e = 0; e < D; ++e) ok &= e == d ? cc[e] < P.ne[e] : cc[e] < P.n[e];
-                fvalid[d] = ok;
-                any |= ok;
-            }
-            if (any) fe = cc[0] + (long long)P.ne[0] * (cc[1] + (long long)P.ne[1] * cc[2]);
-        }
-
-        constexpr int NS = 2 * D + 3;
-        double acc[D][NS];
-#pragma unroll
-        for (int d = 0; d < D; ++d)
-#pragma unroll
-            for (int j = 0; j < NS; ++j) acc[d][j] = 0.0;
-
-        // Software pipelining: the next velocity's fields are loaded while the
-        // current one is processed (when the q-box slots fit in registers).
-        // The loop is unrolled by two over two named register sets, so a
-        // register with a load in flight is never copied: a copy would make
-        // the compiler wait for every outstanding memory operation, the face
-        // value stores included.
-        constexpr bool PREFETCH = NSLOT <= 2 || QS;
-        const void* const src_g = QS ? P.qg : P.g_in;
-        const void* const src_b = QS ? P.qb : P.b_in;
-        RT pa_g[NSLOT], pa_b[NSLOT], pb_g[NSLOT], pb_b[NSLOT];
-        if constexpr (PREFETCH) {
-            load_slots<ST, NSLOT>(P, src_g, src_b, v0 < v1 ? v0 : 0, srcq, pa_g, pa_b);
-        }
-        const long long fstride = P.fv_stride;  // per (d, field) block of FV
-
-        // Maxwellians of the q-box slots by recurrence along velocity axis 0
-        // (when the slot coefficients live in registers)
-        constexpr bool WALKER = KQ;
-        const double h = P.hxi0;
-        const int nvx = P.nv[0];
-        GaussWalk wq[WALKER ? NSLOT : 1];
-        if constexpr (WALKER) {
-#pragma unroll
-            for (int k = 0; k < NSLOT; ++k) wq[k].init(kq[k].inv2RT, h);
-        }
-        int ix = v0 % nvx;
-
-        // one velocity: cur_* hold its prefetched fields, nxt_* receive the next
-        auto velocity = [&](int i, int buf, RT(&cur_g)[NSLOT], RT(&cur_b)[NSLOT], RT(&nxt_g)[NSLOT],
-                            RT(&nxt_b)[NSLOT]) __attribute__((always_inline)) {
-            const Vel v = load_vel(P.vel, i);
-            if constexpr (WALKER) {
-                if (i == v0 || ix % WALK == 0) {
-                    const int a0 = ix - ix % WALK;
-                    const Vel va = a0 == ix ? v : load_vel(P.vel, i - (ix - a0));
-#pragma unroll
-                    for (int k = 0; k < NSLOT; ++k) wq[k].template anchor<D>(kq[k].A, kq[k].inv2RT, kq[k].u, va, h);
-                    for (int j = a0; j < ix; ++j)
-#pragma unroll
-                        for (int k = 0; k < NSLOT; ++k) wq[k].advance();
-                }
-            }
-            // BF16 rows: the raw halves move to the top of an FP32 word
-            const unsigned shift = StoreT<ST>::MIXED ? (unsigned)(row_word(P, i) & 1) << 4 : 0u;
-            CT* const sq0 = sm.q[buf][0];
-            CT* const sq1 = sm.q[buf][1];
-            CT* const sa0 = sm.a[buf][0];
-            CT* const sa1 = sm.a[buf][1];
-            CT q_own[2], a_own[2][D];  // the own cell's q and slopes
-            if constexpr (PREFETCH) {
-                // unconditional loads (the last velocity re-reads itself) keep
-                // the wait counts exact
-                load_slots<ST, NSLOT>(P, src_g, src_b, i + 1 < v1 ? i + 1 : i, srcq, nxt_g, nxt_b);
-            }
-
-            // stage 1: quarter-step fields on the q box
-#pragma unroll
-            for (int k = 0; k < NSLOT; ++k) {
-                if (lq[k] >= 0) {
-                    const int r = lq[k] & 0xFFFFF;
-                    double g, b;
-                    if constexpr (PREFETCH) {
-                        g = slot_value<ST>(cur_g[k], shift);
-                        b = slot_value<ST>(cur_b[k], shift);
-                    } else {
-                        g = state_ld<ST>(P, src_g, i, srcq[k]);
-                        b = state_ld<ST>(P, src_b, i, srcq[k]);
-                    }
-                    double qg, qb;
-                    if constexpr (QS) {
-                        qg = g;
-                        qb = b;
-                    } else if constexpr (KQ) {
-                        const double geq = wq[k].template value<D>(kq[k].A, kq[k].inv2RT, kq[k].u, v);
-                        quarter_step_eq<D>(kq[k], v, geq, g, b, qg, qb);
-                    } else if constexpr (COEF_LDS) {
-                        const double* o = sm.kc + r;
-                        CellCoef kk;
-                        kk.A = o[0 * G::NQ]; kk.inv2RT = o[1 * G::NQ]; kk.cRT2 = o[2 * G::NQ];
-                        kk.beta = o[3 * G::NQ]; kk.betab = o[4 * G::NQ]; kk.eta = o[5 * G::NQ];
-                        kk.hu2 = o[6 * G::NQ]; kk.u[0] = o[7 * G::NQ]; kk.u[1] = o[8 * G::NQ];
-                        kk.u[2] = o[9 * G::NQ];
-                        quarter_step<D>(kk, v, g, b, qg, qb);
-                    } else {
-                        CellCoef kk = load_coef(P.P_in, N, srcq[k]);
-                        quarter_step<D>(kk, v, g, b, qg, qb);
-                    }
-                    if constexpr (DIR) {
-                        if (lq[k] >> 20) {  // Dirichlet ghost: the fixed state's equilibrium
-                            const double* de = P.dir_eq + ((long long)((lq[k] >> 20) - 1) * P.V + i) * 2;
-                            qg = de[0];
-                            qb = de[1];
-                        }
-                    }
-                    sq0[r] = CT(qg);
-                    sq1[r] = CT(qb);
-                    if (k == 0) {  // slot 0 is the own cell
-                        q_own[0] = CT(qg);
-                        q_own[1] = CT(qb);
-                    }
-                }
-            }
-            __syncthreads();
-
-            // stage 2: limited differences on the slope box; the own cell first
-            // (its values stay in registers for stage 3), then the ring
-            {
-                const int ai = G::aidx(tx, ty, tz), qi = G::qidx(tx, ty, tz);
-#pragma unroll
-                for (int e = 0; e < D; ++e) {
-                    const int sq = G::SQ(e);
-#pragma unroll
-                    for (int f = 0; f < 2; ++f) {
-                        const CT* q = f == 0 ? sq0 : sq1;
-                        const CT c = q_own[f];
-                        const CT a = half_van_leer(c - q[qi - sq], q[qi + sq] - c);
-                        (f == 0 ? sa0 : sa1)[e * G::NA + ai] = a;
-                        a_own[f][e] = a;
-                    }
-                }
-            }
-            // the ring: one (point, field) pair per thread and pass, so the
-            // work spreads over all waves of the workgroup
-#pragma unroll
-            for (int k = 0; k < NRING2; ++k) {
-                const int t = tid + k * WG;
-                if (t < 2 * NARING) {
-                    const int f = t >= NARING;
-                    const int h = t - f * NARING;
-                    const int p = slope_ring_point(h);
-                    const int px = p % G::AX, py = (p / G::AX) % G::AY, pz = p / (G::AX * G::AY);
-                    const int qi = (px + 1) + G::QX * ((py + (D >= 2 ? 1 : 0)) + G::QY * (pz + (D >= 3 ? 1 : 0)));
-                    const CT* q = sq0 + f * G::NQ;
-                    CT* a = sa0 + f * (D * G::NA);
-                    const CT c = q[qi];
-#pragma unroll
-                    for (int e = 0; e < D; ++e) {
-                        const int sq = G::SQ(e);
-                        a[e * G::NA + p] = half_van_leer(c - q[qi - sq], q[qi + sq] - c);
-                    }
-                }
-            }
-            __syncthreads();
-
-            // stage 3: left face of the own cell along each d.  Upwind cell u
-            // is c - d (xi_d > 0) or c (xi_d < 0); the own cell's q and slopes
-            // come from registers, the others from LDS.
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                const int dxo = d == 0, dyo = d == 1, dzo = d == 2;
-                const double xd = d == 0 ? v.xi[0] : (d == 1 ? v.xi[1] : v.xi[2]);
-                const int q_m = G::qidx(tx - dxo, ty - dyo, tz - dzo);
-                const int a_m = G::aidx(tx - dxo, ty - dyo, tz - dzo);
-                const int a_mm = G::aidx(tx - 2 * dxo, ty - 2 * dyo, tz - 2 * dzo);
-                const int a_p = G::aidx(tx + dxo, ty + dyo, tz + dzo);
-                CT fv[2];
-#pragma unroll
-                for (int f = 0; f < 2; ++f) {
-                    const CT* sq = f == 0 ? sq0 : sq1;
-                    const CT* sa = f == 0 ? sa0 : sa1;
-                    CT aU[D], aL[D], aR[D];
-                    CT left = 0, right = 0;
-                    if constexpr (SS) {
-                        if (xd >= 0.0) {  // upwind c - d
-#pragma unroll
-                            for (int e = 0; e < D; ++e) aU[e] = sa[e * G::NA + a_m];
-                            left = face_value_single<D, CT>(sq[q_m], aU, d, CT(1), v);
-                        }
-                        if (xd <= 0.0)  // upwind c
-                            right = face_value_single<D, CT>(q_own[f], a_own[f], d, CT(-1), v);
-                    } else {
-                        if (xd >= 0.0) {  // upwind c - d: its left and right neighbours are c - 2d and c
-#pragma unroll
-                            for (int e = 0; e < D; ++e) {
-                                aU[e] = sa[e * G::NA + a_m];
-                                aL[e] = sa[e * G::NA + a_mm];
-                                aR[e] = a_own[f][e];
-                            }
-                            left = face_value_at<D, CT>(sq[q_m], aU, aL, aR, d, CT(1), v);
-                        }
-                        if (xd <= 0.0) {  // upwind c: neighbours c - d and c + d
-#pragma unroll
-                            for (int e = 0; e < D; ++e) {
-                                aU[e] = a_own[f][e];
-                                aL[e] = sa[e * G::NA + a_m];
-                                aR[e] = sa[e * G::NA + a_p];
-                            }
-                            right = face_value_at<D, CT>(q_own[f], aU, aL, aR, d, CT(-1), v);
-                        }
-                    }
-                    fv[f] = xd > 0.0 ? left : (xd < 0.0 ? right : CT(0.5) * (left + right));
-                }
-                const double vg = fv[0], vb2 = fv[1];
-                if (fvalid[d]) {
-                    const long long o = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch + fe;
-                    st_stream<CT>(P.FV, o, vg);
-                    st_stream<CT>(P.FV, o + fstride, vb2);
-                }
-                // weighted velocity products come from the table (uniform)
-                const const_dptr vp = vel_ptr(P.vel, i);
-                acc[d][0] += v.w * vg;
-#pragma unroll
-                for (int e = 0; e < D; ++e) acc[d][1 + e] += vp[VE_WXI0 + e] * vg;
-                acc[d][D + 1] += v.w * vb2;
-#pragma unroll
-                for (int e = 0; e < D; ++e) acc[d][D + 2 + e] += vp[VE_WXX + 3 * d + e] * vg;
-                acc[d][2 * D + 2] += vp[VE_WXI0 + d] * vb2;
-            }
-            if constexpr (WALKER) {
-#pragma unroll
-                for (int k = 0; k < NSLOT; ++k) wq[k].advance();
-                if (++ix == nvx) ix = 0;
-            }
-            // single-buffered: the next velocity must not overwrite q and a
-            // before every thread has read them; double-buffered: the next
-            // velocity writes the other buffer, and the one after that comes
-            // only after two more barriers
-            if constexpr (NBUF == 1) __syncthreads();
-        };
-
-        if constexpr (D <= 2) {
-            int i = v0;
-            for (; i + 1 < v1; i += 2) {
-                velocity(i, 0, pa_g, pa_b, pb_g, pb_b);
-                velocity(i + 1, NBUF - 1, pb_g, pb_b, pa_g, pa_b);
-            }
-            if (i < v1) velocity(i, 0, pa_g, pa_b, pb_g, pb_b);
-        } else {
-            // 3-D: registers allow one set; the copy costs a wait per velocity
-            for (int i = v0; i < v1; ++i) {
-                RT cg[NSLOT], cb[NSLOT];
-#pragma unroll
-                for (int k = 0; k < NSLOT; ++k) {
-                    cg[k] = pa_g[k];
-                    cb[k] = pa_b[k];
-                }
-                velocity(i, 0, cg, cb, pa_g, pa_b);
-            }
-        }
-
-        // partial face sums of this velocity slice
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            if (!fvalid[d]) continue;
-            double* out = P.FS + ((long long)(slice * D + d) * NS) * NE + fe;
-#pragma unroll
-            for (int j = 0; j < NS; ++j) out[(long long)j * NE] = acc[d][j];
-        }
-    }
-};
-
-// ---------------------------------------------------------------------------
-// update kernel: streaming, one thread per cell over a velocity slice.
-// Reads phi^n and the stored phi_bar at the cell's 2D faces, inverts eq.
-// phibar with the face coefficients, forms the microflux (eq. flux) and writes
-// phi^{n+1} (eq. phiupdate).
-// ---------------------------------------------------------------------------
-template <int D, typename ST>
-struct UpdateKernel {
-    using CT = typename StoreT<ST>::C;  // stored face values
-    __device__ static void run(const Problem& P, long long c, int slice, int nslices) {
-        const long long N = P.N, NE = P.NE;
-        const bool inside = c < N;
-        const long long cc = inside ? c : 0;
-        int co[3];
-        {
-            long long r = cc;
-#pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                co[e] = (int)(r % P.n[e]);
-                r /= P.n[e];
-            }
-        }
-        // left and right faces along each d (periodic wrap at the right end);
-        // face indices fit 32 bits (checked at set-up)
-        unsigned fl[D], fr[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            int rc[3] = {co[0], co[1], co[2]};
-            fl[d] = (unsigned)(rc[0] + (long long)P.ne[0] * (rc[1] + (long long)P.ne[1] * rc[2]));
-            rc[d] += 1;
-            if (P.bc[d] == 0 && rc[d] == P.n[d]) rc[d] = 0;
-            fr[d] = (unsigned)(rc[0] + (long long)P.ne[0] * (rc[1] + (long long)P.ne[1] * rc[2]));
-        }
-        const CellCoef k0 = load_coef(P.P_in, N, cc);
-        const CellCoef k1 = load_coef(P.P_out, N, cc);
-        FaceCoef<D> fcl[D], fcr[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const double* F = P.FP + (long long)d * NFP * NE;
-            fcl[d].load(F + fl[d], NE);
-            fcr[d].load(F + fr[d], NE);
-        }
-        const int v0 = (int)((long long)P.V * slice / nslices);
-        const int v1 = (int)((long long)P.V * (slice + 1) / nslices);
-        const long long fstride = P.fv_stride;
-        const double dt = P.dt;
-        // constant parts of eq. phiupdate
-        const double inv_g = 1.0 / (1.0 + 2.0 * k1.beta), inv_b = 1.0 / (1.0 + 2.0 * k1.betab);
-
-        // Maxwellians by recurrence along velocity axis 0 for FP64 storage in
-        // 1-D and 2-D.  The 3-D kernel has no registers to spare, and the FP32
-        // kernel runs a third wave per SIMD without the recurrence state,
-        // which outweighs the exponentials it saves.
-        constexpr bool WALKER = D <= 2 && std::is_same<ST, double>::value;
-        const double h = P.hxi0;
-        const int nvx = P.nv[0];
-        GaussWalk w0, w1, wl[D], wr[D];
-        if constexpr (WALKER) {
-            w0.init(k0.inv2RT, h);
-            w1.init(k1.inv2RT, h);
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                wl[d].init(fcl[d].inv2RT, h);
-                wr[d].init(fcr[d].inv2RT, h);
-            }
-        }
-        int ix = v0 % nvx;
-
-        if constexpr (!StoreT<ST>::MIXED) {
-            // FP64 without the recurrence: two velocities per trip (twice the
-            // loads in flight per wave)
-            constexpr int UNROLL = std::is_same<ST, double>::value && !WALKER ? 2 : 1;
-    #pragma unroll UNROLL
-            for (int i = v0; i < v1; ++i) {
-                const Vel v = load_vel(P.vel, i);
-                if constexpr (WALKER) {
-                    if (i == v0 || ix % WALK == 0) {
-                        const int a0 = ix - ix % WALK;
-                        // a slice starting inside a block walks from its anchor
-                        const Vel va = a0 == ix ? v : load_vel(P.vel, i - (ix - a0));
-                        w0.anchor<D>(k0.A, k0.inv2RT, k0.u, va, h);
-                        w1.anchor<D>(k1.A, k1.inv2RT, k1.u, va, h);
-    #pragma unroll
-                        for (int d = 0; d < D; ++d) {
-                            wl[d].template anchor<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, va, h);
-                            wr[d].template anchor<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, va, h);
-                        }
-                        for (int j = a0; j < ix; ++j) {
-                            w0.advance();
-                            w1.advance();
-    #pragma unroll
-                            for (int d = 0; d < D; ++d) {
-                                wl[d].advance();
-                                wr[d].advance();
-                            }
-                        }
-                    }
-                }
-                const long long vb = (long long)i * P.pitch;
-                const double g = ld<ST>(P.g_in, vb + cc);
-                const double b = ld<ST>(P.b_in, vb + cc);
-                double Fg = 0.0, Fb = 0.0;
-    #pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const long long o = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch;
-                    const double eql = WALKER ? wl[d].template value<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v)
-                                              : maxwellian<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v);
-                    const double eqr = WALKER ? wr[d].template value<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v)
-                                              : maxwellian<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v);
-                    double gl, bl, gr, br;
-                    fcl[d].invert(v, eql, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl, bl);
-                    fcr[d].invert(v, eqr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr, br);
-                    const double sxd = v.xi[d] * P.inv_dx[d];
-                    Fg += sxd * (gr - gl);
-                    Fb += sxd * (br - bl);
-                }
-                double xu0 = 0.0;
-    #pragma unroll
-                for (int d = 0; d < D; ++d) xu0 += v.xi[d] * k0.u[d];
-                const double geq0 = WALKER ? w0.value<D>(k0.A, k0.inv2RT, k0.u, v) : maxwellian<D>(k0.A, k0.inv2RT, k0.u, v);
-                const double beq0 = (v.hx2 + k0.cRT2) * geq0;
-                const double geq1 = WALKER ? w1.value<D>(k1.A, k1.inv2RT, k1.u, v) : maxwellian<D>(k1.A, k1.inv2RT, k1.u, v);
-                const double beq1 = (v.hx2 + k1.cRT2) * geq1;
-                const double Z0 = xu0 - k0.hu2;
-                // eq. phiupdate with dt/(2 tau) = 2 beta and dt S_b = 4 eta Z (g - g_eq)
-                const double gn = (g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg) * inv_g;
-                const double bn = (b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
-                                   4.0 * k0.eta * Z0 * (g - geq0)) *
-                                  inv_b;
-                if (inside) {
-                    st_stream<ST>(P.g_out, vb + cc, gn);
-                    st_stream<ST>(P.b_out, vb + cc, bn);
-                    if constexpr (quarter_stored(D)) {
-                        // next step's phi_bar_plus from the state as stored
-                        double qg, qb;
-                        quarter_step_eq<D>(k1, v, geq1, (double)(ST)gn, (double)(ST)bn, qg, qb);
-                        st_stream<ST>(P.qg, vb + cc, qg);
-                        st_stream<ST>(P.qb, vb + cc, qb);
-                    }
-                }
-                if constexpr (WALKER) {
-                    w0.advance();
-                    w1.advance();
-    #pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        wl[d].advance();
-                        wr[d].advance();
-                    }
-                    if (++ix == nvx) ix = 0;
-                }
-            }
-        } else {
-            // BF16-tail form: the row kind is uniform, so each velocity runs a
-            // copy of the body specialised for FP32 or BF16 rows; no
-            // recurrence for the equilibria
-            auto one = [&](int i, long long off, auto half) __attribute__((always_inline)) {
-                constexpr bool H = decltype(half)::value;
-                const Vel v = load_vel(P.vel, i);
-                const double g = row_ld<ST, H>(P.g_in, off, cc);
-                const double b = row_ld<ST, H>(P.b_in, off, cc);
-                double Fg = 0.0, Fb = 0.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const long long fo = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch;
-                    const double eql = maxwellian<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v);
-                    const double eqr = maxwellian<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v);
-                    double gl, bl, gr, br;
-                    fcl[d].invert(v, eql, ld<CT>(P.FV, fo + fl[d]), ld<CT>(P.FV, fo + fstride + fl[d]), gl, bl);
-                    fcr[d].invert(v, eqr, ld<CT>(P.FV, fo + fr[d]), ld<CT>(P.FV, fo + fstride + fr[d]), gr, br);
-                    const double sxd = v.xi[d] * P.inv_dx[d];
-                    Fg += sxd * (gr - gl);
-                    Fb += sxd * (br - bl);
-                }
-                double xu0 = 0.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) xu0 += v.xi[d] * k0.u[d];
-                const double geq0 = maxwellian<D>(k0.A, k0.inv2RT, k0.u, v);
-                const double beq0 = (v.hx2 + k0.cRT2) * geq0;
-                const double geq1 = maxwellian<D>(k1.A, k1.inv2RT, k1.u, v);
-                const double beq1 = (v.hx2 + k1.cRT2) * geq1;
-                const double Z0 = xu0 - k0.hu2;
-                // eq. phiupdate, as in the plain forms
-                const double gn = (g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg) * inv_g;
-                const double bn = (b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
-                                   4.0 * k0.eta * Z0 * (g - geq0)) *
-                                  inv_b;
-                if (inside) {
-                    row_st_stream<ST, H>(P.g_out, off, cc, gn);
-                    row_st_stream<ST, H>(P.b_out, off, cc, bn);
-                    if constexpr (quarter_stored(D)) {
-                        // next step's phi_bar_plus from the state as stored
-                        double qg, qb;
-                        quarter_step_eq<D>(k1, v, geq1, row_round<ST, H>(gn), row_round<ST, H>(bn), qg, qb);
-                        row_st_stream<ST, H>(P.qg, off, cc, qg);
-                        row_st_stream<ST, H>(P.qb, off, cc, qb);
-                    }
-                }
-            };
-            // the FP32 rows of the slice, then its BF16 rows (every (cell,
-            // velocity) is updated on its own, so the order is free): each
-            // loop holds one straight-line body and the register budget of
-            // the FP32 form
-            for (int i = v0; i < v1; ++i) {
-                const long long o = row_word(P, i);
-                if (!(o & 1)) one(i, o, std::false_type{});
-            }
-            for (int i = v0; i < v1; ++i) {
-                const long long o = row_word(P, i);
-                if (o & 1) one(i, o & ~1LL, std::true_type{});
-            }
-        }
-    }
-};
-
-// waves per SIMD the face-sum kernel is compiled for (register budget; 3-D
-// takes what it needs)
-template <int D>
-constexpr int face_sum_waves() { return D == 1 ? 4 : (D == 2 ? 3 : 1); }
-
-template <int D, typename ST, bool DIR, bool SS>
-__global__ __launch_bounds__(WG, face_sum_waves<D>()) void k_face_sums(Problem P) {
-    using K = FaceSumKernel<D, ST, DIR, SS>;
-    __shared__ typename K::Smem sm;
-    int ntiles = P.tiles1[0] * P.tiles1[1] * P.tiles1[2];
-    int q = xcd_remap(blockIdx.x, gridDim.x);
-    K::run(P, q % ntiles, q / ntiles, P.nslices, sm);
-}
-
-// Batched face sums: one launch for every tile of every problem of a storage
-// class.  Persistent: the grid covers the resident slots and the workgroups
-// take (cost-sorted, largest first) items from a device queue: an atomic
-// counter, so a workgroup that finishes early takes the next item.  Which
-// workgroup computes an item does not change its result.  The launch resets
-// the other kernel's counter (that kernel's previous launch has finished and
-// its next one starts after this one), so no memset enters a graph.
-// Problems of different dimension share the launch; LDS is the union of their
-// needs.
-// The item index is uniform across the workgroup; readfirstlane tells the
-// compiler so, and the item and its problem descriptor are then read through
-// the constant address space: scalar loads into SGPRs instead of a copy of
-// the descriptor in vector registers (the FP32 1-D/2-D face-sum class then
-// runs 3 waves per SIMD, like the single-problem kernel).  Forcing the update
-// class to 3 waves as well spills registers and is slower.
-__device__ __forceinline__ int next_item(int* queue, int* slot) {
-    if (threadIdx.x == 0) *slot = atomicAdd(queue, 1);
-    __syncthreads();
-    const int w = __builtin_amdgcn_readfirstlane(*slot);
-    __syncthreads();  // every thread has read the slot before it is refilled
-    return w;
-}
-
-// word-wise copy of a uniform descriptor through the constant address space
-template <typename T>
-__device__ __forceinline__ T load_uniform(const T* p) {
-    static_assert(sizeof(T) % 4 == 0, "descriptor size");
-    typedef const __attribute__((address_space(4))) unsigned* const_uptr;
-    const const_uptr s = (const_uptr)(const void*)p;
-    unsigned words[sizeof(T) / 4];
-#pragma unroll
-    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) words[k] = s[k];
-    T r;
-    __builtin_memcpy(&r, words, sizeof(T));
-    return r;
-}
-
-template <typename ST, int MAXD, bool DIR, bool SS>
-__global__ __launch_bounds__(WG) void k_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems,
-                                                          int* queue, int* other) {
-    __shared__ union U {
-        typename FaceSumKernel<1, ST, DIR, SS>::Smem s1;
-        typename FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR, SS>::Smem s2;
-        typename FaceSumKernel<MAXD >= 3 ? 3 : 1, ST, DIR, SS>::Smem s3;
-    } sm;
-    __shared__ int slot;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *other = 0;
-    for (int w = next_item(queue, &slot); w < nitems; w = next_item(queue, &slot)) {
-        const WorkItem it = load_uniform(items + w);
-        const Problem P = load_uniform(probs + it.prob);
-        if (P.D == 1) FaceSumKernel<1, ST, DIR, SS>::run(P, it.tile, it.slice, P.nslices, sm.s1);
-        else if (MAXD >= 2 && P.D == 2)
-            FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR, SS>::run(P, it.tile, it.slice, P.nslices, sm.s2);
-        else if (MAXD >= 3)
-            FaceSumKernel<MAXD >= 3 ? 3 : 1, ST, DIR, SS>::run(P, it.tile, it.slice, P.nslices, sm.s3);
-    }
-}
 
 // update grid: blocks of 256 consecutive cells x velocity slices
 template <int D, typename ST>
@@ -1359,165 +129,14 @@ __global__ __launch_bounds__(WG) void k_update_batched(const Problem* probs, con
     }
 }
 
-// ---------------------------------------------------------------------------
-// face closure: W_f, coefficients, flux moments (one thread per (d, face))
-// ---------------------------------------------------------------------------
-__device__ void face_close_one(const Problem& P, long long idx) {
-    const int D = P.D;
-    const long long NE = P.NE;
-    if (idx >= NE * D) return;
-    const int d = (int)(idx / NE);
-    const long long f = idx - (long long)d * NE;
-    long long r = f;
-    int cc[3];
-    for (int e = 0; e < 3; ++e) {
-        cc[e] = (int)(r % P.ne[e]);
-        r /= P.ne[e];
-    }
-    for (int e = 0; e < D; ++e)
-        if (e != d && cc[e] >= P.n[e]) return;
-    if (P.bc[d] == 0 && cc[d] >= P.n[d]) return;
-
-    const int NS = 2 * D + 3;
-    double S[MAX_NSUM];
-    for (int j = 0; j < NS; ++j) S[j] = 0.0;
-    for (int s = 0; s < P.nslices; ++s) {
-        const double* in = P.FS + ((long long)(s * D + d) * NS) * NE + f;
-        for (int j = 0; j < NS; ++j) S[j] += in[(long long)j * NE];
-    }
-    double Wf[5] = {S[0], S[1], D >= 2 ? S[2] : 0.0, D >= 3 ? S[3] : 0.0, 0.0};
-    Wf[D + 1] = S[D + 1];
-    Prim q = primitives(P, Wf);
-    if (q.bad) {
-        raise_error(P.err);
-        return;
-    }
-    const double beta = 0.25 * P.dt * q.inv_tau_g;
-    const double betab = beta * P.Pr;
-    const double eta = beta * (P.Pr - 1.0);
-    const double A = maxwell_prefactor(P, q.rho, q.RT);
-    const double inv2RT = 0.5 / q.RT;
-    const double hu2 = 0.5 * (q.u[0] * q.u[0] + q.u[1] * q.u[1] + q.u[2] * q.u[2]);
-    const double cRT2 = 0.5 * P.c_int * q.RT;
-
-    // separable discrete moments of the face Maxwellian: M[k][p] = sum_m w_m xi_m^p E_k(m)
-    double M[3][4];
-    int off = 0;
-    for (int k = 0; k < 3; ++k) {
-        for (int p = 0; p < 4; ++p) M[k][p] = 0.0;
-        if (k >= D) {
-            M[k][0] = 1.0;
-            continue;
-        }
-        for (int m = 0; m < P.nv[k]; ++m) {
-            double x = P.axis_xi[off + m];
-            double e = P.axis_w[off + m] * exp(-(x - q.u[k]) * (x - q.u[k]) * inv2RT);
-            M[k][0] += e;
-            M[k][1] += e * x;
-            M[k][2] += e * x * x;
-            M[k][3] += e * x * x * x;
-        }
-        off += P.nv[k];
-    }
-    auto prod0 = [&](int skip1, int skip2) {
-        double p = 1.0;
-        for (int k = 0; k < D; ++k)
-            if (k != skip1 && k != skip2) p *= M[k][0];
-        return p;
-    };
-    // equilibrium flux moments through a face with normal d
-    double E1 = A * M[d][1] * prod0(d, -1);
-    double E2[3];
-    for (int e = 0; e < D; ++e)
-        E2[e] = e == d ? A * M[d][2] * prod0(d, -1) : A * M[d][1] * M[e][1] * prod0(d, e);
-    double X3 = M[d][3] * prod0(d, -1);
-    for (int e = 0; e < D; ++e)
-        if (e != d) X3 += M[d][1] * M[e][2] * prod0(d, e);
-    X3 *= A;
-    double E3 = 0.5 * X3 + cRT2 * E1;
-    double EZ = -hu2 * E1;
-    for (int e = 0; e < D; ++e) EZ += q.u[e] * E2[e];
-
-    // phi at the face is affine in phi_bar (inversion of eq. phibar), so the
-    // flux moments follow from the velocity sums of phi_bar and the
-    // equilibrium moments above.
-    const double ig = 1.0 / (1.0 + beta), ib = 1.0 / (1.0 + betab);
-    double Gm = (S[1 + d] + beta * E1) * ig;
-    double Gp[3];
-    double ZG = -hu2 * Gm;
-    for (int e = 0; e < D; ++e) {
-        Gp[e] = (S[D + 2 + e] + beta * E2[e]) * ig;
-        ZG += q.u[e] * Gp[e];
-    }
-    double Ge = (S[2 * D + 2] + betab * E3 + eta * (ZG - EZ)) * ib;
-
-    double* Go = P.G + (long long)d * (D + 2) * NE + f;
-    Go[0] = Gm;
-    for (int e = 0; e < D; ++e) Go[(long long)(1 + e) * NE] = Gp[e];
-    Go[(long long)(D + 1) * NE] = Ge;
-
-    double* F = P.FP + (long long)d * NFP * NE + f;
-    F[PF_A * NE] = A;
-    F[PF_INV2RT * NE] = inv2RT;
-    F[PF_CRT2 * NE] = cRT2;
-    F[PF_IG * NE] = ig;
-    F[PF_BG * NE] = beta * ig;
-    F[PF_IB * NE] = ib;
-    F[PF_BB * NE] = betab * ib;
-    F[PF_EB * NE] = eta * ib;
-    F[PF_HU2 * NE] = hu2;
-    for (int e = 0; e < 3; ++e) F[(PF_U0 + e) * NE] = q.u[e];
-}
-
 __global__ __launch_bounds__(WG) void k_face_close(Problem P) {
     face_close_one(P, (long long)blockIdx.x * WG + threadIdx.x);
-}
-
-// ---------------------------------------------------------------------------
-// cell closure: W^{n+1} = W^n - dt sum_d (G_right - G_left)/dx_d; coefs at n+1
-// ---------------------------------------------------------------------------
-__device__ void cell_close_one(const Problem& P, long long c) {
-    if (c >= P.N) return;
-    const int D = P.D;
-    const long long N = P.N, NE = P.NE;
-    long long r = c;
-    int cc[3];
-    for (int e = 0; e < 3; ++e) {
-        cc[e] = (int)(r % P.n[e]);
-        r /= P.n[e];
-    }
-    long long fl = cc[0] + (long long)P.ne[0] * (cc[1] + (long long)P.ne[1] * cc[2]);
-    double Wn[5];
-    for (int k = 0; k < D + 2; ++k) Wn[k] = P.W_in[k * N + c];
-    for (int d = 0; d < D; ++d) {
-        int rc[3] = {cc[0], cc[1], cc[2]};
-        rc[d] += 1;
-        if (P.bc[d] == 0 && rc[d] == P.n[d]) rc[d] = 0;
-        long long fr = rc[0] + (long long)P.ne[0] * (rc[1] + (long long)P.ne[1] * rc[2]);
-        const double* Gd = P.G + (long long)d * (D + 2) * NE;
-        for (int k = 0; k < D + 2; ++k)
-            Wn[k] -= P.dt * P.inv_dx[d] * (Gd[k * NE + fr] - Gd[k * NE + fl]);
-    }
-    for (int k = 0; k < D + 2; ++k) P.W_out[k * N + c] = Wn[k];
-    Prim q = primitives(P, Wn);
-    if (q.bad) raise_error(P.err);
-    write_cell_coefs(P, P.P_out, N, c, q);
 }
 
 __global__ __launch_bounds__(WG) void k_cell_close(Problem P) {
     cell_close_one(P, (long long)blockIdx.x * WG + threadIdx.x);
 }
 
-// per-problem thread ranges for the batched per-face / per-cell launches
-__device__ __forceinline__ int find_problem(const long long* offsets, int nprob, long long g) {
-    int lo = 0, hi = nprob - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) / 2;
-        if (offsets[mid] <= g) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
 
 __global__ __launch_bounds__(WG) void k_face_close_batched(const Problem* probs, const long long* offsets,
                                                            int nprob, long long total) {
@@ -1607,29 +226,15 @@ hipError_t launch_init(const Problem& P, const double* rho, const double* u, con
 }
 
 hipError_t launch_face_sums(const Problem& P, hipStream_t s) {
-    unsigned nb = (unsigned)(P.tiles1[0] * P.tiles1[1] * P.tiles1[2] * P.nslices);
-    if (P.recon == 0) {
-        if (P.dir_eq) {
-#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT, true, false>), dim3(nb), dim3(WG), 0, s, P)
-            CDG_DISPATCH(P.storage, P.D, CDG_L);
-#undef CDG_L
-        } else {
-#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT, false, false>), dim3(nb), dim3(WG), 0, s, P)
-            CDG_DISPATCH(P.storage, P.D, CDG_L);
-#undef CDG_L
-        }
-    } else {
-        if (P.dir_eq) {
-#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT, true, true>), dim3(nb), dim3(WG), 0, s, P)
-            CDG_DISPATCH(P.storage, P.D, CDG_L);
-#undef CDG_L
-        } else {
-#define CDG_L(DD, TT) hipLaunchKernelGGL((k_face_sums<DD, TT, false, true>), dim3(nb), dim3(WG), 0, s, P)
-            CDG_DISPATCH(P.storage, P.D, CDG_L);
-#undef CDG_L
-        }
-    }
-    return hipGetLastError();
+    if (P.D == 1) return launch_face_sums_d1(P, s);
+    if (P.D == 2) return launch_face_sums_d2(P, s);
+    return launch_face_sums_d3(P, s);
+}
+
+int face_sum_blocks_per_cu(int D, int storage, int tile) {
+    if (D == 1) return face_sum_blocks_per_cu_d1(storage, tile);
+    if (D == 2) return face_sum_blocks_per_cu_d2(storage, tile);
+    return face_sum_blocks_per_cu_d3(storage, tile);
 }
 
 hipError_t launch_update(const Problem& P, hipStream_t s) {
@@ -1641,17 +246,12 @@ hipError_t launch_update(const Problem& P, hipStream_t s) {
 }
 
 int tile_blocks_per_cu(int D, int storage, bool update) {
+    if (!update) return face_sum_blocks_per_cu(D, storage, 0);
     int n = 0;
     hipError_t e = hipSuccess;
-    if (update) {
 #define CDG_L(DD, TT) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_update<DD, TT>), WG, 0)
-        CDG_DISPATCH(storage, D, CDG_L);
+    CDG_DISPATCH(storage, D, CDG_L);
 #undef CDG_L
-    } else {
-#define CDG_L(DD, TT) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums<DD, TT, false, false>), WG, 0)
-        CDG_DISPATCH(storage, D, CDG_L);
-#undef CDG_L
-    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return 0;
@@ -1701,43 +301,6 @@ hipError_t launch_to_f64(const Problem& P, const void* src, int row0, int nrows,
         }                                                            \
     } while (0)
 
-hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int grid,
-                                    int maxd, int storage, bool dirichlet, bool single_slope, int* queue,
-                                    int* other, hipStream_t s) {
-    if (nitems <= 0) return hipSuccess;
-#define CDG_B(DIRV, SSV)                                                                                     \
-    do {                                                                                                     \
-        if ((STORAGE_) == 0) {                                                                               \
-            if (maxd == 1) CDG_LB(double, 1, DIRV, SSV);                                                     \
-            else if (maxd == 2) CDG_LB(double, 2, DIRV, SSV);                                                \
-            else CDG_LB(double, 3, DIRV, SSV);                                                               \
-        } else if ((STORAGE_) == 1) {                                                                        \
-            if (maxd == 1) CDG_LB(float, 1, DIRV, SSV);                                                      \
-            else if (maxd == 2) CDG_LB(float, 2, DIRV, SSV);                                                 \
-            else CDG_LB(float, 3, DIRV, SSV);                                                                \
-        } else {                                                                                             \
-            if (maxd == 1) CDG_LB(Bf16Tail, 1, DIRV, SSV);                                                   \
-            else if (maxd == 2) CDG_LB(Bf16Tail, 2, DIRV, SSV);                                              \
-            else CDG_LB(Bf16Tail, 3, DIRV, SSV);                                                             \
-        }                                                                                                    \
-    } while (0)
-#define CDG_LB(TT, MD, DIRV, SSV)                                                                            \
-    hipLaunchKernelGGL((k_face_sums_batched<TT, MD, DIRV, SSV>), dim3(grid), dim3(WG), 0, s, probs, items,  \
-                       nitems, queue, other)
-#define STORAGE_ storage
-    if (dirichlet) {
-        if (single_slope) CDG_B(true, true);
-        else CDG_B(true, false);
-    } else {
-        if (single_slope) CDG_B(false, true);
-        else CDG_B(false, false);
-    }
-#undef STORAGE_
-#undef CDG_LB
-#undef CDG_B
-    return hipGetLastError();
-}
-
 hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, int nitems, int grid, int maxd,
                                  int storage, int* queue, int* other, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
@@ -1750,17 +313,12 @@ hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, in
 }
 
 int batched_blocks_per_cu(int maxd, int storage, bool update) {
+    if (!update) return batched_face_blocks_per_cu(maxd, storage);
     int n = 0;
     hipError_t e = hipSuccess;
-    if (update) {
 #define CDG_L(TT, MD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_update_batched<TT, MD>), WG, 0)
-        CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
+    CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
 #undef CDG_L
-    } else {
-#define CDG_L(TT, MD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums_batched<TT, MD, false, false>), WG, 0)
-        CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
-#undef CDG_L
-    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return 0;

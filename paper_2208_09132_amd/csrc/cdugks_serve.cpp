@@ -68,6 +68,7 @@ int device_cus() {
 struct TuneEntry {
     int upd_slices = 0;   // 0 = the occupancy rule
     int grid_factor = 1;  // persistent grid = factor x resident slots
+    int face_tile = 0;    // face-sum tile shape of single-problem launches (0 = default)
 };
 
 std::mutex g_tune_mu;
@@ -89,10 +90,14 @@ void tune_load_locked() {
     if (!path) return;
     FILE* f = fopen(path, "r");
     if (!f) return;
-    char key[128];
-    int us, gf;
-    // one entry per line: "key upd_slices grid_factor"
-    while (fscanf(f, "%127s %d %d", key, &us, &gf) == 3) g_tune[key] = TuneEntry{us, gf};
+    // one entry per line: "key upd_slices grid_factor [face_tile]"
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        char key[128];
+        int us = 0, gf = 1, ft = 0;
+        const int got = sscanf(line, "%127s %d %d %d", key, &us, &gf, &ft);
+        if (got >= 3) g_tune[key] = TuneEntry{us, gf, got == 4 ? ft : 0};
+    }
     fclose(f);
 }
 
@@ -102,7 +107,9 @@ void tune_save_locked() {
     std::string tmp = std::string(path) + ".tmp";
     FILE* f = fopen(tmp.c_str(), "w");
     if (!f) return;
-    for (auto& kv : g_tune) fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.upd_slices, kv.second.grid_factor);
+    for (auto& kv : g_tune)
+        fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.upd_slices, kv.second.grid_factor,
+                kv.second.face_tile);
     fclose(f);
     rename(tmp.c_str(), path);
 }
@@ -222,6 +229,10 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
         for (int p = 0; p < 2; ++p) {
             Problem P = c->P;
             set_pingpong(P, c->r, c->base, c->cur ^ p);
+            // batched launches run the default tile shape of each dimension
+            // (the same result as any other shape)
+            P.tile = 0;
+            for (int d = 0; d < 3; ++d) P.tiles1[d] = c->r.tiles1_def[d];
             probs[p].push_back(P);
         }
         face_off[j] = ft;
@@ -243,7 +254,7 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
         const Resolved& r = ctxs[j]->r;
         const int s = class_of(r);
         maxd[s] = std::max(maxd[s], r.D);
-        const int nt = r.tiles1[0] * r.tiles1[1] * r.tiles1[2];
+        const int nt = r.tiles1_def[0] * r.tiles1_def[1] * r.tiles1_def[2];
         const double vpt = (double)r.V / r.nslices;
         for (int sl = 0; sl < r.nslices; ++sl)
             for (int t = 0; t < nt; ++t) {
@@ -675,15 +686,47 @@ int cdugks_autotune(cdugks_ctx* c, int steps_per_trial) {
     if (!c || steps_per_trial <= 0) return fail(CDUGKS_ERR_INVALID, "bad argument");
     if (c->in_batch) return fail(CDUGKS_ERR_BUSY, "context belongs to a batch");
     if (c->sticky) return fail(c->sticky, "context is in an error state");
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(CDUGKS_ERR_DEVICE, "event create");
+    // face-sum tile shapes usable for this problem: each times steps_per_trial
+    // face-sum launches on the current state (rerunning the first phase of a
+    // step changes nothing the next step reads before rewriting it)
+    int best_tile = 0;
+    {
+        double best_ft = 1e300;
+        for (int t = 0; t < tile_shape_count(c->r.D); ++t) {
+            if (!face_tile_usable(c->r, t)) continue;
+            Resolved rt = c->r;
+            set_face_tile(rt, t);
+            Problem P = c->P;
+            set_pingpong(P, c->r, c->base, c->cur);
+            P.tile = t;
+            for (int d = 0; d < 3; ++d) P.tiles1[d] = rt.tiles1[d];
+            float ms = 0.f;
+            hipError_t he = launch_face_sums(P, c->stream);  // warm-up
+            if (he == hipSuccess) he = hipEventRecord(e0, c->stream);
+            for (int k = 0; k < steps_per_trial && he == hipSuccess; ++k) he = launch_face_sums(P, c->stream);
+            if (he == hipSuccess) he = hipEventRecord(e1, c->stream);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (he != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return hip_fail(he, "face-sum tile trial");
+            }
+            if (ms < best_ft) {
+                best_ft = ms;
+                best_tile = t;
+            }
+        }
+    }
     // candidates: update slices (occupancy rule x {1/2, 1, 2, 4}) and the
     // persistent grid factor {1, 2}; every candidate gives the same result
     const int base = c->r.nslices_upd;
     int cand_slices[4] = {std::max(1, base / 2), base, base * 2, base * 4};
     int best_s = base, best_g = 1;
     double best_t = 1e300;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return fail(CDUGKS_ERR_DEVICE, "event create");
     const Resolved saved = c->r;
     const Problem savedP = c->P;
     int rc = CDUGKS_OK;
@@ -695,7 +738,7 @@ int cdugks_autotune(cdugks_ctx* c, int steps_per_trial) {
             {
                 std::lock_guard<std::mutex> lock(g_tune_mu);
                 tune_load_locked();
-                g_tune[class_key(c->r)] = TuneEntry{sl, gf};
+                g_tune[class_key(c->r)] = TuneEntry{sl, gf, best_tile};
             }
             cdugks_batch* b = nullptr;
             cdugks_ctx* one[1] = {c};
@@ -719,11 +762,21 @@ int cdugks_autotune(cdugks_ctx* c, int steps_per_trial) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    // the context takes the winners; its captured step graphs hold the old
+    // launch shapes and are captured again at the next step
     c->r.nslices_upd = best_s;
     c->P.nslices_upd = best_s;
+    set_face_tile(c->r, best_tile);
+    c->P.tile = c->r.tile;
+    for (int d = 0; d < 3; ++d) c->P.tiles1[d] = c->r.tiles1[d];
+    for (int k = 0; k < 2; ++k)
+        if (c->graph[k]) {
+            (void)hipGraphExecDestroy(c->graph[k]);
+            c->graph[k] = nullptr;
+        }
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
-        g_tune[class_key(c->r)] = TuneEntry{best_s, best_g};
+        g_tune[class_key(c->r)] = TuneEntry{best_s, best_g, best_tile};
         tune_save_locked();
     }
     if (rc) return rc;
@@ -733,6 +786,8 @@ int cdugks_autotune(cdugks_ctx* c, int steps_per_trial) {
 }  // extern "C"
 
 namespace cdg {
-// Used by resolve(): the tuned update slices of a problem class, if any.
+// Used by resolve(): the tuned update slices and face-sum tile shape of a
+// problem class, if any.
 int tuned_update_slices(const Resolved& r) { return tune_lookup(r).upd_slices; }
+int tuned_face_tile(const Resolved& r) { return tune_lookup(r).face_tile; }
 }  // namespace cdg

@@ -135,20 +135,37 @@ def test_batched_workload_equals_alone_and_matches_oracle():
 
 
 def test_autotune_keeps_results():
-    p = wl.kelvin_helmholtz(n=48, nv=10)
-    a = cd.Solver(p)
-    a.step(6)
-    ref = a.moments()
-    a.close()
-    t = cd.Solver(p)
-    t.autotune(2)  # advances by its trial steps
-    t.close()
-    c = cd.Solver(p)  # picks the tuned split for this class
-    c.step(6)
-    got = c.moments()
-    c.close()
-    for x, y in zip(ref, got):
-        assert np.array_equal(x, y)
+    """The autotuner's choices (face-sum tile shape, update split, batched
+    grid) change no result: a context created after tuning, which takes the
+    tuned shapes, and the tuned context itself after its trial steps, give
+    bitwise the results of untuned runs."""
+    for p in (wl.kelvin_helmholtz(n=48, nv=10), wl.random_fourier(3, [20, 12, 12], [5, 5, 5], wl.SplitMix64(2),
+                                                                    amp=0.2, Kn=1e-2, storage="f32")):
+        a = cd.Solver(p)
+        a.step(6)
+        ref = a.moments()
+        a.close()
+        t = cd.Solver(p)
+        t.autotune(2)  # advances by its trial steps
+        _log(f"autotuned dim {p['dim']}: launch shape {t.launch_info()}")
+        tuned_steps = t.info()[2]
+        t.close()
+        c = cd.Solver(p)  # picks the tuned shapes for this class
+        c.step(6)
+        got = c.moments()
+        c.close()
+        for x, y in zip(ref, got):
+            assert np.array_equal(x, y)
+        b = cd.Solver(p)
+        b.step(tuned_steps + 6)
+        ref2 = b.moments()
+        b.close()
+        t = cd.Solver(p)
+        t.autotune(2)
+        t.step(6)
+        for x, y in zip(ref2, t.moments()):
+            assert np.array_equal(x, y)
+        t.close()
 
 
 def test_server_results_equal_alone_and_budget_admission():

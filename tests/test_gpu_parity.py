@@ -246,3 +246,66 @@ def test_kelvin_helmholtz_full_size_conservation_and_stationarity():
     Wb = s.conserved()
     s.close()
     assert np.array_equal(Wa, Wb)
+
+
+def test_face_sum_tile_shapes_give_bitwise_equal_results():
+    """Every face-sum tile shape a problem can use (cdugks_params.face_tile)
+    gives bitwise the same result, on grids whose extents are not multiples
+    of the tiles (ragged tiles in every shape); a non-default shape in a batch
+    (which runs the default shape) too; and one non-default shape against
+    the oracle."""
+    cases = [(wl.kelvin_helmholtz(n=40, nv=12), 4, 5),
+             (dict(wl.kelvin_helmholtz(n=40, nv=12), storage="f32"), 4, 5),
+             (wl.random_fourier(3, [37, 9, 14], [5, 6, 5], wl.SplitMix64(6), amp=0.2, Kn=1e-2,
+                                storage="f32"), 6, 3)]
+    for p, nshapes, steps in cases:
+        ref = None
+        for k in range(1, nshapes + 1):
+            q = dict(p, face_tile=k)
+            try:
+                s = cd.Solver(q)
+            except cd.CdugksError as e:
+                _log(f"  dim {p['dim']} {p['storage']}: shape {k} not available ({e})")
+                continue
+            assert s.launch_info()[0] == k
+            s.step(steps)
+            m = s.moments()
+            s.close()
+            _log(f"tile shape {k}: dim {p['dim']} {p['storage']} n={p['n']}")
+            if ref is None:
+                ref = m
+            else:
+                for a, b in zip(ref, m):
+                    assert np.array_equal(a, b), (p["dim"], p["storage"], k)
+    # a context with a non-default shape in a batch
+    p = wl.kelvin_helmholtz(n=40, nv=12)
+    solo = cd.Solver(dict(p, face_tile=2))
+    solo.step(5)
+    want = solo.moments()
+    solo.close()
+    a, b = cd.Solver(dict(p, face_tile=2)), cd.Solver(wl.sod(n=50, nv=16))
+    bt = cd.Batch([a, b], chunk_steps=2)
+    bt.step(5)
+    bt.close()
+    for x, y in zip(a.moments(), want):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
+    check_parity(dict(p, face_tile=4), 5, 1e-12)
+
+
+def test_face_sum_tile_requests_outside_the_list_are_refused():
+    p = wl.kelvin_helmholtz(n=24, nv=8)
+    for bad in (-1, 5):
+        with pytest.raises(cd.CdugksError) as ei:
+            cd.Solver(dict(p, face_tile=bad))
+        assert ei.value.code == cd.ERR_INVALID
+    d = wl.sod(n=64, nv=16, boundary="dirichlet")  # 1-D has one shape
+    with pytest.raises(cd.CdugksError):
+        cd.Solver(dict(d, face_tile=2))
+    q = wl.random_fourier(2, [21, 18], [7, 6], wl.SplitMix64(8), amp=0.2, Kn=1e-2)
+    q["bc"] = ["dirichlet", "periodic"]
+    q["dirichlet"] = [[[1.3, 0.2, -0.1, 1.2], [0.9, -0.1, 0.05, 0.8]], None]
+    with pytest.raises(cd.CdugksError) as ei:  # Dirichlet sides run the default shape only
+        cd.Solver(dict(q, face_tile=2))
+    assert "not available" in str(ei.value)
