@@ -32,7 +32,8 @@ import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 # sources that decide what a kernel launch reads and writes
-DIGEST_FILES = ["csrc/cdugks_kernels.hip", "csrc/cdugks_internal.h", "csrc/cdugks_api.cpp"]
+DIGEST_FILES = ["csrc/cdugks_kernels.hip", "csrc/cdugks_device.h", "csrc/cdugks_face_sums.hip",
+                "csrc/cdugks_batched.hip", "csrc/cdugks_internal.h", "csrc/cdugks_api.cpp"]
 COPY_PATTERN = r"k_to_f64<double>"
 
 
