@@ -10,7 +10,7 @@
  *   4. limited slopes of the slopes ("gradients of the gradients")       Sec. 2.1
  *   5. phi_bar at each face centre at t_{n+1/2}: value at the
  *      characteristic foot x_f - h xi, upwind by the sign of xi.A         eq. relation
- *   6. face conserved variables from sums of phi_bar (a = 0)            eq. rhobar..rhoEbar
+ *   6. face conserved variables from sums of phi_bar                    eq. rhobar..rhoEbar
  *   7. face equilibrium, relaxation times, inversion of phi_bar -> phi  eq. phibar
  *   8. microflux moments and the W update (minus sign: outward flux)    eq. rhoupdate..rhoEupdate
  *   9. phi update with the trapezoid collision term                      eq. phiupdate
@@ -24,7 +24,12 @@
  *     classic upwind reconstruction phi_bar_plus(x_u) + (x_f - h xi - x_u) . sigma(u);
  *   - W^{n+1} = W^n - dt/|V| * sum of outward flux moments (the sign printed
  *     in eq. rhoupdate is inconsistent with eqs. implicit and phiupdate);
- *   - the source integral in the energy update is zero when a = 0;
+ *   - the source integrals in the W update are the velocity moments of the
+ *     sources themselves, 0 and rho a for g and rho u.a for b (the Z term
+ *     integrates to zero), with the cell's state at t_n (rectangle rule);
+ *   - with an external acceleration a, the velocity derivatives in S_g, S_b
+ *     (eqs. gsource, bsource) are evaluated on the local equilibrium (see
+ *     sources() below);
  *   - a velocity with xi_d = 0 takes the mean of both one-sided values;
  *   - ghost cells: periodic wraps, outflow copies the boundary cell,
  *     Dirichlet holds the discrete equilibrium of the side's fixed state; a
@@ -209,6 +214,32 @@ static double Zfun(const oracle_state* s, const prim_t* q, const double* xi)
     return xu - 0.5 * u2;
 }
 
+/* Source terms S_g, S_b of eqs. gsource and bsource at one velocity, for the
+ * state q (primitives) with distributions g, b and equilibria geq, beq.
+ *   S_g = -a . grad_xi g
+ *   S_b = (Z/tau_bg)(g - g_eq) + a . xi g - a . grad_xi b
+ * The paper leaves the discretisation of the velocity derivative open.  It is
+ * taken on the local equilibrium, the usual force model of the DUGKS family:
+ *   grad_xi g ~ grad_xi g_eq = -(xi - u)/(R T) g_eq,
+ *   grad_xi b ~ grad_xi b_eq = xi g_eq - (xi - u)/(R T) b_eq   (eq. beq),
+ * so that
+ *   S_g = a.(xi - u)/(R T) g_eq,
+ *   S_b = (Z/tau_bg)(g - g_eq) + a.xi (g - g_eq) + a.(xi - u)/(R T) b_eq.
+ * The velocity integrals of these are those of the exact sources: 0 and
+ * rho a for S_g, rho u.a for S_b.  S_g does not depend on g, and S_b is
+ * affine in g, so eq. phibar can still be inverted velocity by velocity. */
+static void sources(const oracle_state* s, const prim_t* q, const double* xi, double g, double geq,
+                    double beq, double* Sg, double* Sb)
+{
+    double axu = 0.0, ax = 0.0;
+    for (int d = 0; d < s->D; ++d) {
+        axu += s->p.accel[d] * (xi[d] - q->u[d]);
+        ax += s->p.accel[d] * xi[d];
+    }
+    *Sg = axu / q->RT * geq;
+    *Sb = Zfun(s, q, xi) * q->inv_tau_bg * (g - geq) + ax * (g - geq) + axu / q->RT * beq;
+}
+
 void oracle_equilibrium_moments(const oracle_state* s, double rho, const double* u,
                                 double T, double* out)
 {
@@ -386,8 +417,7 @@ static int one_step(oracle_state* s)
     if (bad) { free(cp); return -4; }
 
     /* 2. phi_bar_plus = phi + (h/2) Omega + (h/2) S on the ghost-extended
-     *    grid (eq. phibarplus), with S_g = 0 and S_b = (Z/tau_bg)(g - g_eq)
-     *    for a = 0 (eqs. gsource, bsource). */
+     *    grid (eq. phibarplus), with the sources of eqs. gsource, bsource. */
     double* qg = (double*)malloc(sizeof(double) * NE * V);
     double* qb = (double*)malloc(sizeof(double) * NE * V);
 #pragma omp parallel for schedule(static)
@@ -396,14 +426,17 @@ static int one_step(oracle_state* s)
         ext_coords(s, e, c);
         const int ds = dirichlet_side(s, c);
         if (ds >= 0) {
-            /* the ghost holds the equilibrium of the fixed state, so its
-             * relaxation and S_b terms vanish and phi_bar_plus = phi_eq */
+            /* the ghost holds the equilibrium of the fixed state: its
+             * relaxation and Z terms vanish, the acceleration terms remain */
             const prim_t* q = &s->dprim[ds];
             for (long i = 0; i < V; ++i) {
                 const double* xi = s->xi + 3 * i;
                 double geq = g_equilibrium(s, q, xi);
-                qg[e * V + i] = geq;
-                qb[e * V + i] = b_equilibrium(s, q, xi, geq);
+                double beq = b_equilibrium(s, q, xi, geq);
+                double Sg, Sb;
+                sources(s, q, xi, geq, geq, beq, &Sg, &Sb);
+                qg[e * V + i] = geq + 0.5 * h * Sg;
+                qb[e * V + i] = beq + 0.5 * h * Sb;
             }
             continue;
         }
@@ -414,10 +447,11 @@ static int one_step(oracle_state* s)
             double g = s->g[r * V + i], b = s->b[r * V + i];
             double geq = g_equilibrium(s, q, xi);
             double beq = b_equilibrium(s, q, xi, geq);
-            double Sb = Zfun(s, q, xi) * q->inv_tau_bg * (g - geq);
+            double Sg, Sb;
+            sources(s, q, xi, g, geq, beq, &Sg, &Sb);
             double Og = (geq - g) * q->inv_tau_g;
             double Ob = (beq - b) * q->inv_tau_b;
-            qg[e * V + i] = g + 0.5 * h * Og;
+            qg[e * V + i] = g + 0.5 * h * Og + 0.5 * h * Sg;
             qb[e * V + i] = b + 0.5 * h * Ob + 0.5 * h * Sb;
         }
     }
@@ -549,7 +583,9 @@ static int one_step(oracle_state* s)
                 bface[i] = vb / nside;
             }
 
-            /* 6. W at the face from sums of phi_bar (eqs. rhobar..rhoEbar, a = 0) */
+            /* 6. W at the face from sums of phi_bar (eqs. rhobar..rhoEbar):
+             *    rho u gains (h/2) rho a, rho E gains (h/2) (rho u).a with the
+             *    face momentum just formed */
             double Wf[5] = {0, 0, 0, 0, 0};
             for (long i = 0; i < V; ++i) {
                 const double* xi = s->xi + 3 * i;
@@ -557,6 +593,8 @@ static int one_step(oracle_state* s)
                 for (int k = 0; k < D; ++k) Wf[1 + k] += s->w[i] * xi[k] * gface[i];
                 Wf[D + 1] += s->w[i] * bface[i];
             }
+            for (int k = 0; k < D; ++k) Wf[1 + k] += 0.5 * h * Wf[0] * s->p.accel[k];
+            for (int k = 0; k < D; ++k) Wf[D + 1] += 0.5 * h * Wf[1 + k] * s->p.accel[k];
 
             /* 7. face equilibrium and relaxation times from W_f, then invert
              *    eq. phibar: phi = (phi_bar + (h/2) phi_eq/tau + (h/2) S)/(1 + h/(2 tau)).
@@ -567,8 +605,11 @@ static int one_step(oracle_state* s)
                 const double* xi = s->xi + 3 * i;
                 double geq = g_equilibrium(s, &q, xi);
                 double beq = b_equilibrium(s, &q, xi, geq);
-                double gval = (gface[i] + 0.5 * h * q.inv_tau_g * geq) / (1.0 + 0.5 * h * q.inv_tau_g);
-                double Sb = Zfun(s, &q, xi) * q.inv_tau_bg * (gval - geq);
+                double Sg, Sb;
+                sources(s, &q, xi, 0.0, geq, beq, &Sg, &Sb);  /* S_g does not depend on g */
+                double gval = (gface[i] + 0.5 * h * q.inv_tau_g * geq + 0.5 * h * Sg) /
+                              (1.0 + 0.5 * h * q.inv_tau_g);
+                sources(s, &q, xi, gval, geq, beq, &Sg, &Sb);
                 double bval = (bface[i] + 0.5 * h * q.inv_tau_b * beq + 0.5 * h * Sb) /
                               (1.0 + 0.5 * h * q.inv_tau_b);
                 gface[i] = gval;
@@ -608,9 +649,9 @@ static int one_step(oracle_state* s)
         (out) = fc_[0] + nf[d][0] * (fc_[1] + nf[d][1] * fc_[2]);                      \
     } while (0)
 
-    /* 8. W^{n+1} = W^n - (dt/|V_j|) sum_faces (A . flux moments): for a
-     *    Cartesian cell, - dt sum_d (G_{right} - G_{left}) / dx_d.  The source
-     *    integrals vanish for a = 0. */
+    /* 8. W^{n+1} = W^n - (dt/|V_j|) sum_faces (A . flux moments) + dt (source
+     *    integrals at t_n): for a Cartesian cell, - dt sum_d (G_{right} -
+     *    G_{left}) / dx_d, plus dt (0, rho a, (rho u).a). */
     double* Wn = (double*)malloc(sizeof(double) * N * NW);
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < N; ++c) {
@@ -626,6 +667,11 @@ static int one_step(oracle_state* s)
                 div += (Gf[d][fr * NW + k] - Gf[d][fl * NW + k]) / s->dx[d];
             }
             Wn[c * NW + k] = s->W[c * NW + k] - dt * div;
+        }
+        const double* W0 = s->W + c * NW;
+        for (int k = 0; k < D; ++k) {
+            Wn[c * NW + 1 + k] += dt * W0[0] * s->p.accel[k];
+            Wn[c * NW + D + 1] += dt * W0[1 + k] * s->p.accel[k];
         }
     }
 
@@ -659,8 +705,9 @@ static int one_step(oracle_state* s)
                 Fg += xi[d] * (gf[d][fr[d] * V + i] - gf[d][fl[d] * V + i]) / s->dx[d];
                 Fb += xi[d] * (bf[d][fr[d] * V + i] - bf[d][fl[d] * V + i]) / s->dx[d];
             }
-            double Sb = Zfun(s, &q0, xi) * q0.inv_tau_bg * (g - geq0);
-            double gn = (g + 0.5 * dt * (geq1 * q1.inv_tau_g + (geq0 - g) * q0.inv_tau_g) - dt * Fg) /
+            double Sg, Sb;
+            sources(s, &q0, xi, g, geq0, beq0, &Sg, &Sb);
+            double gn = (g + 0.5 * dt * (geq1 * q1.inv_tau_g + (geq0 - g) * q0.inv_tau_g) - dt * Fg + dt * Sg) /
                         (1.0 + 0.5 * dt * q1.inv_tau_g);
             double bn = (b + 0.5 * dt * (beq1 * q1.inv_tau_b + (beq0 - b) * q0.inv_tau_b) - dt * Fb + dt * Sb) /
                         (1.0 + 0.5 * dt * q1.inv_tau_b);

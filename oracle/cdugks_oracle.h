@@ -44,6 +44,8 @@ typedef struct {
     double mu_ref, T_ref, omega;
     double tau;
     double dt;            /* time step */
+    double accel[3];      /* external acceleration a (eqs. gPDE, bPDE); zero
+                             gives the scheme without it */
     int reconstruction;   /* ORC_RECON_SLOPES_OF_SLOPES (the paper's Sec. 2.1:
                              the face gradient is itself reconstructed from
                              limited derivatives of the slopes) or

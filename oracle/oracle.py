@@ -58,6 +58,7 @@ class _Params(ctypes.Structure):
         ("omega", ctypes.c_double),
         ("tau", ctypes.c_double),
         ("dt", ctypes.c_double),
+        ("accel", ctypes.c_double * 3),
         ("reconstruction", ctypes.c_int),
     ]
 
@@ -137,7 +138,8 @@ class Oracle:
     'periodic'/'outflow'/'dirichlet'), nv, vmin, vmax, quad, gamma, Pr, R,
     relax ('mu' or 'tau'), mu_ref, T_ref, omega, tau, dt, reconstruction
     ('slopes_of_slopes', the paper's, or 'single_slope'), and for Dirichlet
-    dimensions ``dirichlet[d] = [[rho, u_1..u_D, T] low side, [..] high side]``.
+    dimensions ``dirichlet[d] = [[rho, u_1..u_D, T] low side, [..] high side]``,
+    and optionally ``accel`` (the external acceleration a, D components).
     """
 
     def __init__(self, prob: dict):
@@ -178,6 +180,9 @@ class Oracle:
         p.tau = math.inf if tau is None else float(tau)
         p.dt = float(prob["dt"])
         p.reconstruction = RECON[prob.get("reconstruction", "slopes_of_slopes")]
+        acc = prob.get("accel") or [0.0] * D
+        for d in range(D):
+            p.accel[d] = float(acc[d])
         self._p = p
         self.D = D
         self.N = int(np.prod([prob["n"][d] for d in range(D)]))

@@ -11,8 +11,13 @@ reconstruction or the sign of the flux would miss the 50-digit result.
 The readings are those the oracle documents: Van Leer of the one-sided
 derivatives, face value q(u) + delta s_d(u) - h xi.(s(u) + delta t_d(u))
 (the single-slope option: q(u) + delta s_d(u) - h xi.s(u)),
-mean of the two one-sided values for xi_d = 0, outward-flux sign, zero
-source integral in the energy update, outflow ghosts clamp the index.
+mean of the two one-sided values for xi_d = 0, outward-flux sign, outflow
+ghosts clamp the index; with an external acceleration a (the cases with
+accel), the sources of eqs. gsource and bsource with the velocity derivative
+taken on the local equilibrium, grad_xi g ~ -(xi - u)/(R T) g_eq and
+grad_xi b ~ xi g_eq - (xi - u)/(R T) b_eq, the face moments of eqs. rhoubar
+and rhoEbar, and the source integrals (0, rho a, rho u.a) at t_n in the W
+update (without a, the zero source integral of the Z term).
 """
 import itertools
 
@@ -61,6 +66,7 @@ class Brute:
         self.dt = M(P["dt"])
         self.h = self.dt / 2
         self.single_slope = P.get("reconstruction") == "single_slope"
+        self.a = [M(v) for v in P.get("accel", [0.0, 0.0])]
 
     # ---- Sec. 2: primitives, relaxation times, equilibria ----
     def prim(self, W):
@@ -88,10 +94,29 @@ class Brute:
     def Z(self, q, i):
         return sum(self.xi[i][d] * q["u"][d] for d in range(2)) - (q["u"][0] ** 2 + q["u"][1] ** 2) / 2
 
+    def S(self, q, i, g):
+        """eqs. gsource, bsource at velocity i for the state q and the value g
+        of the mass distribution: S_g = -a.grad_xi g, S_b = Z (g - g_eq)/tau_bg
+        + a.xi g - a.grad_xi b, with grad_xi g = -(xi - u) g_eq/(R T) and
+        grad_xi b = xi g_eq - (xi - u) b_eq/(R T) (derivatives of eqs. geq, beq)."""
+        RT = self.R * q["T"]
+        ge, be = self.geq(q, i), self.beq(q, i)
+        grad_g = [-(self.xi[i][d] - q["u"][d]) * ge / RT for d in range(2)]
+        grad_b = [self.xi[i][d] * ge - (self.xi[i][d] - q["u"][d]) * be / RT for d in range(2)]
+        Sg = -sum(self.a[d] * grad_g[d] for d in range(2))
+        Sb = (self.Z(q, i) * q["inv_tau_bg"] * (g - ge) + sum(self.a[d] * self.xi[i][d] for d in range(2)) * g
+              - sum(self.a[d] * grad_b[d] for d in range(2)))
+        return Sg, Sb
+
     # ---- cells, ghosts ----
     def cell(self, x, y):
-        """Source cell of a (possibly ghost) position: periodic wrap or outflow clamp."""
+        """Source cell of a (possibly ghost) position: periodic wrap or outflow
+        clamp; ('dir', d, side) for a ghost outside along a Dirichlet dimension
+        (the highest such dimension)."""
         c = [x, y]
+        for d in (1, 0):
+            if self.bc[d] == "dirichlet" and not 0 <= c[d] < self.n[d]:
+                return ("dir", d, 0 if c[d] < 0 else 1)
         for d in range(2):
             if self.bc[d] == "periodic":
                 c[d] %= self.n[d]
@@ -99,18 +124,29 @@ class Brute:
                 c[d] = min(max(c[d], 0), self.n[d] - 1)
         return c[0] + self.n[0] * c[1]
 
+    def ghost_state(self, d, side):
+        """The primitives of a Dirichlet side's fixed state (rho, u_x, u_y, T)."""
+        rho, ux, uy, T = [M(v) for v in self.P["dirichlet"][d][side]]
+        E = (ux ** 2 + uy ** 2) / 2 + self.R * T / (self.gamma - 1)
+        return self.prim([rho, rho * ux, rho * uy, rho * E])
+
     def step(self, g, b, W):
         D, V, h, dt = self.D, self.V, self.h, self.dt
         N = self.n[0] * self.n[1]
         qc = [self.prim(W[j]) for j in range(N)]
 
-        # eq. phibarplus with S_g = 0, S_b = Z (g - g_eq) / tau_bg
+        # eq. phibarplus
         def qbar(f, j, i):
+            if isinstance(j, tuple):  # Dirichlet ghost: the side state's equilibrium
+                q = self.ghost_state(j[1], j[2])
+                ge, be = self.geq(q, i), self.beq(q, i)
+                Sg, Sb = self.S(q, i, ge)
+                return ge + h / 2 * Sg if f == 0 else be + h / 2 * Sb
             q = qc[j]
             ge = self.geq(q, i)
+            Sg, Sb = self.S(q, i, g[j][i])
             if f == 0:
-                return g[j][i] + h / 2 * (ge - g[j][i]) / q["tau_g"]
-            Sb = self.Z(q, i) * q["inv_tau_bg"] * (g[j][i] - ge)
+                return g[j][i] + h / 2 * (ge - g[j][i]) / q["tau_g"] + h / 2 * Sg
             return b[j][i] + h / 2 * (self.beq(q, i) - b[j][i]) / q["tau_b"] + h / 2 * Sb
 
         QB = {}
@@ -161,8 +197,8 @@ class Brute:
         # faces along d: left faces of cells x = 0..n_d (n_d + 1 faces for
         # outflow, n_d for periodic)
         def faces(d):
-            nx = self.n[0] + (1 if d == 0 and self.bc[0] == "outflow" else 0)
-            ny = self.n[1] + (1 if d == 1 and self.bc[1] == "outflow" else 0)
+            nx = self.n[0] + (1 if d == 0 and self.bc[0] != "periodic" else 0)
+            ny = self.n[1] + (1 if d == 1 and self.bc[1] != "periodic" else 0)
             return [(x, y) for y in range(ny) for x in range(nx)]
 
         phi_face = {}
@@ -170,19 +206,22 @@ class Brute:
             for (x, y) in faces(d):
                 gb = [face_bar(0, x, y, i, d) for i in range(V)]
                 bb = [face_bar(1, x, y, i, d) for i in range(V)]
-                # eqs. rhobar..rhoEbar with a = 0
-                Wf = [sum(self.w[i] * gb[i] for i in range(V)),
-                      sum(self.w[i] * self.xi[i][0] * gb[i] for i in range(V)),
-                      sum(self.w[i] * self.xi[i][1] * gb[i] for i in range(V)),
-                      sum(self.w[i] * bb[i] for i in range(V))]
+                # eqs. rhobar..rhoEbar
+                rho_f = sum(self.w[i] * gb[i] for i in range(V))
+                mom_f = [sum(self.w[i] * self.xi[i][d] * gb[i] for i in range(V)) + h / 2 * rho_f * self.a[d]
+                         for d in range(2)]
+                ene_f = sum(self.w[i] * bb[i] for i in range(V)) + h / 2 * sum(mom_f[d] * self.a[d] for d in range(2))
+                Wf = [rho_f, mom_f[0], mom_f[1], ene_f]
                 qf = self.prim(Wf)
                 gf, bf = [], []
                 for i in range(V):
                     ge, be = self.geq(qf, i), self.beq(qf, i)
-                    # invert eq. phibar: g first, then S_b with the face g, then b
+                    # invert eq. phibar: g first (S_g does not depend on g),
+                    # then S_b with the face g, then b
                     ag, ab = h / (2 * qf["tau_g"]), h / (2 * qf["tau_b"])
-                    gi = (gb[i] + ag * ge) / (1 + ag)
-                    Sb = self.Z(qf, i) * qf["inv_tau_bg"] * (gi - ge)
+                    Sg, _ = self.S(qf, i, M(0))
+                    gi = (gb[i] + ag * ge + h / 2 * Sg) / (1 + ag)
+                    _, Sb = self.S(qf, i, gi)
                     bi = (bb[i] + ab * be + h / 2 * Sb) / (1 + ab)
                     gf.append(gi)
                     bf.append(bi)
@@ -208,22 +247,24 @@ class Brute:
                     for i in range(V):
                         Fg[i] += self.xi[i][d] * (right[0][i] - left[0][i]) / self.dx[d]
                         Fb[i] += self.xi[i][d] * (right[1][i] - left[1][i]) / self.dx[d]
-                # eqs. rhoupdate..rhoEupdate, outward flux (minus), zero source integral
+                # eqs. rhoupdate..rhoEupdate, outward flux (minus); the source
+                # integrals at t_n are 0, rho a and rho u.a
                 Wn = [W[j][0] - dt * sum(self.w[i] * Fg[i] for i in range(V)),
-                      W[j][1] - dt * sum(self.w[i] * self.xi[i][0] * Fg[i] for i in range(V)),
-                      W[j][2] - dt * sum(self.w[i] * self.xi[i][1] * Fg[i] for i in range(V)),
-                      W[j][3] - dt * sum(self.w[i] * Fb[i] for i in range(V))]
+                      W[j][1] - dt * sum(self.w[i] * self.xi[i][0] * Fg[i] for i in range(V)) + dt * W[j][0] * self.a[0],
+                      W[j][2] - dt * sum(self.w[i] * self.xi[i][1] * Fg[i] for i in range(V)) + dt * W[j][0] * self.a[1],
+                      W[j][3] - dt * sum(self.w[i] * Fb[i] for i in range(V))
+                      + dt * (W[j][1] * self.a[0] + W[j][2] * self.a[1])]
                 q0, q1 = qc[j], self.prim(Wn)
                 gr, br = [], []
                 for i in range(V):
                     ge0, be0 = self.geq(q0, i), self.beq(q0, i)
                     ge1, be1 = self.geq(q1, i), self.beq(q1, i)
-                    S = self.Z(q0, i) * q0["inv_tau_bg"] * (g[j][i] - ge0)
+                    Sg, Sb = self.S(q0, i, g[j][i])
                     # eq. phiupdate
-                    gn = (g[j][i] + dt / 2 * (ge1 / q1["tau_g"] + (ge0 - g[j][i]) / q0["tau_g"]) - dt * Fg[i]) / (
-                        1 + dt / (2 * q1["tau_g"]))
+                    gn = (g[j][i] + dt / 2 * (ge1 / q1["tau_g"] + (ge0 - g[j][i]) / q0["tau_g"]) - dt * Fg[i]
+                          + dt * Sg) / (1 + dt / (2 * q1["tau_g"]))
                     bn = (b[j][i] + dt / 2 * (be1 / q1["tau_b"] + (be0 - b[j][i]) / q0["tau_b"]) - dt * Fb[i]
-                          + dt * S) / (1 + dt / (2 * q1["tau_b"]))
+                          + dt * Sb) / (1 + dt / (2 * q1["tau_b"]))
                     gr.append(gn)
                     br.append(bn)
                 g1.append(gr)
@@ -232,13 +273,22 @@ class Brute:
         return g1, b1, W1
 
 
-@pytest.mark.parametrize("bc_y,recon", [("outflow", "slopes_of_slopes"), ("periodic", "slopes_of_slopes"),
-                                         ("outflow", "single_slope")])
-def test_one_step_matches_50_digit_brute_force(bc_y, recon):
+@pytest.mark.parametrize("bc_y,recon,accel", [("outflow", "slopes_of_slopes", None),
+                                               ("periodic", "slopes_of_slopes", None),
+                                               ("outflow", "single_slope", None),
+                                               ("dirichlet", "slopes_of_slopes", None),
+                                               ("outflow", "slopes_of_slopes", [0.7, -1.3]),
+                                               ("periodic", "single_slope", [-0.4, 0.9]),
+                                               ("dirichlet", "slopes_of_slopes", [0.3, -1.1])])
+def test_one_step_matches_50_digit_brute_force(bc_y, recon, accel):
     orc.build(force=False)
     P = dict(dim=2, n=[4, 3], lo=[0.0, -0.5], hi=[1.0, 0.25], bc=["periodic", bc_y], nv=[3, 4],
              vmin=[-2.0, -1.5], vmax=[2.0, 2.5], quad="trapezoid", gamma=7.0 / 5.0, Pr=2.0 / 3.0, R=0.5,
              relax="mu", mu_ref=0.02, T_ref=1.0, omega=0.5, dt=0.01, reconstruction=recon)
+    if accel is not None:
+        P["accel"] = accel
+    if bc_y == "dirichlet":
+        P["dirichlet"] = [None, [[1.3, 0.2, -0.1, 1.2], [0.9, -0.1, 0.05, 0.8]]]
     N, V = 12, 12
     rng = np.random.default_rng(2208)
     # smooth-ish positive distributions with random perturbations, off
