@@ -135,6 +135,18 @@ typedef struct {
                                64-wide 3-D shape does not in FP64); else
                                CDUGKS_ERR_INVALID.  Every shape gives bitwise the
                                same result. */
+    double accel[3];        /* external acceleration a (e.g. gravity; Sec. 2,
+                               eqs. gPDE, bPDE), components >= dim ignored; all
+                               zero = none.  The sources of eqs. gsource and
+                               bsource take the velocity derivative on the local
+                               equilibrium, grad_xi g ~ -(xi - u)/(R T) g_eq and
+                               grad_xi b ~ xi g_eq - (xi - u)/(R T) b_eq; the face
+                               moments gain (h/2) rho a and (h/2) rho u.a (eqs.
+                               rhoubar, rhoEbar) and the W update the source
+                               integrals dt (0, rho a, rho u.a) at t_n.  Needs the
+                               paper's reconstruction and the default face tile;
+                               single problems only (batches and the server
+                               refuse it with CDUGKS_ERR_INVALID). */
 } cdugks_params;
 
 typedef struct cdugks_ctx cdugks_ctx;

@@ -56,7 +56,8 @@ class cdugks_params(ctypes.Structure):
                 ("L_ref", ctypes.c_double), ("rho_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
                 ("mu_ref", ctypes.c_double), ("tau", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("dt", ctypes.c_double), ("storage", ctypes.c_int), ("velocity_slices", ctypes.c_int),
-                ("reconstruction", ctypes.c_int), ("face_tile", ctypes.c_int)]
+                ("reconstruction", ctypes.c_int), ("face_tile", ctypes.c_int),
+                ("accel", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -171,6 +172,9 @@ def describe(prob: dict):
     pa.reconstruction = RECON[prob.get("reconstruction", "slopes_of_slopes")]
     pa.velocity_slices = int(prob.get("velocity_slices", 0))
     pa.face_tile = int(prob.get("face_tile", 0))
+    acc = prob.get("accel") or [0.0] * D
+    for d in range(D):
+        pa.accel[d] = float(acc[d])
     return sp, ve, pa
 
 

@@ -129,6 +129,13 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
     if (pa->reconstruction != CDUGKS_RECON_SLOPES_OF_SLOPES && pa->reconstruction != CDUGKS_RECON_SINGLE_SLOPE)
         return fail(CDUGKS_ERR_INVALID, "unknown reconstruction %d", pa->reconstruction);
     r.recon = pa->reconstruction;
+    for (int d = 0; d < 3; ++d) {
+        r.accel[d] = d < D ? pa->accel[d] : 0.0;
+        if (!std::isfinite(r.accel[d])) return fail(CDUGKS_ERR_INVALID, "accel[%d] is not finite", d);
+        r.has_accel = r.has_accel || r.accel[d] != 0.0;
+    }
+    if (r.has_accel && r.recon != CDUGKS_RECON_SLOPES_OF_SLOPES)
+        return fail(CDUGKS_ERR_INVALID, "an external acceleration needs the paper's reconstruction");
     r.gamma = pa->gamma;
     r.Pr = pa->Pr;
     r.R = pa->R;
@@ -313,7 +320,7 @@ void set_face_tile(Resolved& r, int tile) {
 bool face_tile_usable(const Resolved& r, int tile) {
     if (tile < 0 || tile >= tile_shape_count(r.D)) return false;
     if (tile == 0) return true;
-    if (r.any_dirichlet || r.recon != CDUGKS_RECON_SLOPES_OF_SLOPES) return false;
+    if (r.any_dirichlet || r.recon != CDUGKS_RECON_SLOPES_OF_SLOPES || r.has_accel) return false;
     if (!face_tile_fits(r.D, tile, r.storage == CDUGKS_STORE_F64 ? 8 : 4)) return false;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
@@ -391,6 +398,9 @@ void velocity_tables(const Resolved& r, std::vector<double>& vel, std::vector<do
         }
         v[VE_W] = w;
         v[VE_HX2] = 0.5 * x2;
+        double ax = 0.0;
+        for (int d = 0; d < D; ++d) ax += r.accel[d] * nodes[d][m[d]];
+        v[VE_AX] = ax;
         for (int d = 0; d < D; ++d) {
             v[VE_WXI0 + d] = w * nodes[d][m[d]];
             for (int e = 0; e < D; ++e) v[VE_WXX + 3 * d + e] = w * nodes[d][m[d]] * nodes[e][m[e]];
@@ -401,9 +411,13 @@ void velocity_tables(const Resolved& r, std::vector<double>& vel, std::vector<do
     for (int d = 0; d < 3; ++d) axis.insert(axis.end(), wts[d].begin(), wts[d].end());
 }
 
-// Discrete equilibria of the Dirichlet states, [2 d + side][V][g_eq, b_eq]
-// (eqs. geq, beq; the ghost cells hold them, so their quarter-step value is
-// the equilibrium itself).  Sides of non-Dirichlet dimensions stay zero.
+// Quarter-step values of the Dirichlet ghosts, [2 d + side][V][g, b]: the
+// ghost cells hold the discrete equilibria of the side states (eqs. geq,
+// beq), so relaxation and the Z source vanish and the quarter-step value is
+// the equilibrium itself, plus (h/2) S of an external acceleration,
+// a.(xi - u)/(R T) times g_eq and b_eq (eqs. gsource, bsource with the
+// velocity derivative on the equilibrium).  Sides of non-Dirichlet
+// dimensions stay zero.
 void dirichlet_tables(const Resolved& r, const std::vector<double>& vel, std::vector<double>& out) {
     const int D = r.D;
     out.assign((size_t)2 * D * r.V * 2, 0.0);
@@ -425,8 +439,12 @@ void dirichlet_tables(const Resolved& r, const std::vector<double>& vel, std::ve
                     c2 += x * x;
                 }
                 const double geq = A * std::exp(-c2 * inv2RT);
-                o[2 * i] = geq;
-                o[2 * i + 1] = (v[VE_HX2] + cRT2) * geq;
+                const double beq = (v[VE_HX2] + cRT2) * geq;
+                double au = 0.0;
+                for (int e = 0; e < D; ++e) au += r.accel[e] * st[1 + e];
+                const double c = 0.5 * r.dt * inv2RT * (v[VE_AX] - au);  // (h/2) a.(xi - u)/(R T)
+                o[2 * i] = geq + c * geq;
+                o[2 * i + 1] = beq + c * beq;
             }
         }
     }
@@ -480,6 +498,8 @@ void fill_problem(const Resolved& r, char* base, Problem& P) {
     P.rows = r.storage == CDUGKS_STORE_F32_BF16TAIL ? (const long long*)(base + r.off_rows) : nullptr;
     P.recon = r.recon;
     P.tile = r.tile;
+    P.has_accel = r.has_accel ? 1 : 0;
+    for (int d = 0; d < 3; ++d) P.accel[d] = r.accel[d];
 }
 
 // Rows of the BF16-tail form: velocity i is a tail row when, for every

@@ -340,7 +340,7 @@ __device__ __forceinline__ CellCoef load_coef(const double* Pc, long long N, lon
 }
 
 struct Vel {
-    double xi[3], w, hx2, lam2[3];
+    double xi[3], w, hx2, lam2[3], ax;
 };
 
 // The velocity table is read-only for the whole launch: reading it through the
@@ -356,16 +356,20 @@ __device__ __forceinline__ Vel load_vel(const double* vel, int i) {
     const_dptr v = vel_ptr(vel, i);
     Vel r;
     r.xi[0] = v[0]; r.xi[1] = v[1]; r.xi[2] = v[2];
-    r.w = v[VE_W]; r.hx2 = v[VE_HX2];
+    r.w = v[VE_W]; r.hx2 = v[VE_HX2]; r.ax = v[VE_AX];
     r.lam2[0] = v[VE_LAM0]; r.lam2[1] = v[VE_LAM0 + 1]; r.lam2[2] = v[VE_LAM0 + 2];
     return r;
 }
 
 // Z and the quarter-step fields at one (cell, velocity), given g_eq:
-// phi_bar_plus = phi + (h/2)(phi_eq - phi)/tau + (h/2) S, S_b = Z (g - g_eq)/tau_bg.
-template <int D>
+// phi_bar_plus = phi + (h/2)(phi_eq - phi)/tau + (h/2) S (eq. phibarplus),
+// S_b = Z (g - g_eq)/tau_bg + ... .  ACC adds the external acceleration's
+// terms of the sources (eqs. gsource, bsource) with the velocity derivative
+// taken on the equilibrium: S_g = a.(xi - u)/(R T) g_eq and, in S_b,
+// a.xi (g - g_eq) + a.(xi - u)/(R T) b_eq; (h/2)/(R T) = (dt/2)/(2 R T).
+template <int D, bool ACC = false>
 __device__ __forceinline__ void quarter_step_eq(const CellCoef& k, const Vel& v, double geq, double g, double b,
-                                                double& qg, double& qb) {
+                                                double& qg, double& qb, const Problem* P = nullptr) {
     double xu = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) xu += v.xi[d] * k.u[d];
@@ -373,6 +377,14 @@ __device__ __forceinline__ void quarter_step_eq(const CellCoef& k, const Vel& v,
     double Z = xu - k.hu2;
     qg = g + k.beta * (geq - g);
     qb = b + k.betab * (beq - b) + k.eta * Z * (g - geq);
+    if constexpr (ACC) {
+        double au = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) au += P->accel[d] * k.u[d];
+        const double c = 0.5 * P->dt * k.inv2RT * (v.ax - au);
+        qg += c * geq;
+        qb += 0.25 * P->dt * v.ax * (g - geq) + c * beq;
+    }
 }
 
 // Value of phi_bar at a face centre at t_{n+1/2} from the upwind cell u,
@@ -451,6 +463,27 @@ struct FaceCoef {
         gF = ig * vg + bg * geq;
         bF = ib * vb + bb * beq + eb * Z * (gF - geq);
     }
+    // The same with an external acceleration a: the face's (h/2) S terms
+    // (eqs. gsource, bsource, velocity derivative on the equilibrium), with
+    // au = a.u_f and c2 = (dt/2)/(2 R T_f) prepared once per face.
+    double au, c2;
+    __device__ void prepare_accel(const double* a, double dt) {
+        au = 0.0;
+#pragma unroll
+        for (int e = 0; e < D; ++e) au += a[e] * u[e];
+        c2 = 0.5 * dt * inv2RT;
+    }
+    __device__ __forceinline__ void invert_accel(const Vel& v, double dt, double geq, double vg, double vb,
+                                                 double& gF, double& bF) const {
+        double xu = 0.0;
+#pragma unroll
+        for (int e = 0; e < D; ++e) xu += v.xi[e] * u[e];
+        double beq = (v.hx2 + cRT2) * geq;
+        double Z = xu - hu2;
+        const double c = c2 * (v.ax - au);
+        gF = ig * vg + bg * geq + ig * c * geq;
+        bF = ib * vb + bb * beq + eb * Z * (gF - geq) + ib * (0.25 * dt * v.ax * (gF - geq) + c * beq);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -515,7 +548,9 @@ struct GaussWalk {
 // budget of the others unchanged).
 // SS: the single-slope reconstruction option (stage 3 reads only the upwind
 // cell's slopes).
-template <int D, typename ST, bool DIR = false, bool SS = false, int TID = 0>
+// ACC: the problem has an external acceleration (stage 1 adds its source
+// terms; the a = 0 instantiations keep their register budget).
+template <int D, typename ST, bool DIR = false, bool SS = false, int TID = 0, bool ACC = false>
 struct FaceSumKernel {
     using G = Geo<D, TID>;
     static constexpr int NT = G::NT;
@@ -736,7 +771,7 @@ struct FaceSumKernel {
                         qb = b;
                     } else {
                         const double geq = wq[k].template value<D>(kq[k].A, kq[k].inv2RT, kq[k].u, v);
-                        quarter_step_eq<D>(kq[k], v, geq, g, b, qg, qb);
+                        quarter_step_eq<D, ACC>(kq[k], v, geq, g, b, qg, qb, &P);
                     }
                     if constexpr (DIR) {
                         if (lq[k] >> 20) {  // Dirichlet ghost: the fixed state's equilibrium
@@ -908,7 +943,10 @@ struct FaceSumKernel {
 // phibar with the face coefficients, forms the microflux (eq. flux) and writes
 // phi^{n+1} (eq. phiupdate).
 // ---------------------------------------------------------------------------
-template <int D, typename ST>
+// ACC: the problem has an external acceleration (face inversion, the cell
+// source of eq. phiupdate and, in 3-D, the next quarter-step fields carry
+// its terms).
+template <int D, typename ST, bool ACC = false>
 struct UpdateKernel {
     using CT = typename StoreT<ST>::C;  // stored face values
     __device__ static void run(const Problem& P, long long c, int slice, int nslices) {
@@ -943,6 +981,17 @@ struct UpdateKernel {
             const double* F = P.FP + (long long)d * NFP * NE;
             fcl[d].load(F + fl[d], NE);
             fcr[d].load(F + fr[d], NE);
+            if constexpr (ACC) {
+                fcl[d].prepare_accel(P.accel, P.dt);
+                fcr[d].prepare_accel(P.accel, P.dt);
+            }
+        }
+        // the cell's source terms at t_n: dt S_g = c0 g_eq, dt S_b = dt a.xi (g - g_eq) + c0 b_eq
+        // with c0 = dt a.(xi - u)/(R T) = 2 dt (a.xi - a.u)/(2 R T)
+        double au0 = 0.0;
+        if constexpr (ACC) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) au0 += P.accel[d] * k0.u[d];
         }
         const int v0 = (int)((long long)P.V * slice / nslices);
         const int v1 = (int)((long long)P.V * (slice + 1) / nslices);
@@ -1012,8 +1061,13 @@ struct UpdateKernel {
                     const double eqr = WALKER ? wr[d].template value<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v)
                                               : maxwellian<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v);
                     double gl, bl, gr, br;
-                    fcl[d].invert(v, eql, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl, bl);
-                    fcr[d].invert(v, eqr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr, br);
+                    if constexpr (ACC) {
+                        fcl[d].invert_accel(v, dt, eql, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl, bl);
+                        fcr[d].invert_accel(v, dt, eqr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr, br);
+                    } else {
+                        fcl[d].invert(v, eql, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl, bl);
+                        fcr[d].invert(v, eqr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr, br);
+                    }
                     const double sxd = v.xi[d] * P.inv_dx[d];
                     Fg += sxd * (gr - gl);
                     Fb += sxd * (br - bl);
@@ -1027,17 +1081,23 @@ struct UpdateKernel {
                 const double beq1 = (v.hx2 + k1.cRT2) * geq1;
                 const double Z0 = xu0 - k0.hu2;
                 // eq. phiupdate with dt/(2 tau) = 2 beta and dt S_b = 4 eta Z (g - g_eq)
-                const double gn = (g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg) * inv_g;
-                const double bn = (b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
-                                   4.0 * k0.eta * Z0 * (g - geq0)) *
-                                  inv_b;
+                double gn = g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg;
+                double bn = b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
+                            4.0 * k0.eta * Z0 * (g - geq0);
+                if constexpr (ACC) {
+                    const double c0 = 2.0 * dt * k0.inv2RT * (v.ax - au0);
+                    gn += c0 * geq0;
+                    bn += dt * v.ax * (g - geq0) + c0 * beq0;
+                }
+                gn *= inv_g;
+                bn *= inv_b;
                 if (inside) {
                     st_stream<ST>(P.g_out, vb + cc, gn);
                     st_stream<ST>(P.b_out, vb + cc, bn);
                     if constexpr (quarter_stored(D)) {
                         // next step's phi_bar_plus from the state as stored
                         double qg, qb;
-                        quarter_step_eq<D>(k1, v, geq1, (double)(ST)gn, (double)(ST)bn, qg, qb);
+                        quarter_step_eq<D, ACC>(k1, v, geq1, (double)(ST)gn, (double)(ST)bn, qg, qb, &P);
                         st_stream<ST>(P.qg, vb + cc, qg);
                         st_stream<ST>(P.qb, vb + cc, qb);
                     }
@@ -1069,8 +1129,13 @@ struct UpdateKernel {
                     const double eql = maxwellian<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v);
                     const double eqr = maxwellian<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v);
                     double gl, bl, gr, br;
-                    fcl[d].invert(v, eql, ld<CT>(P.FV, fo + fl[d]), ld<CT>(P.FV, fo + fstride + fl[d]), gl, bl);
-                    fcr[d].invert(v, eqr, ld<CT>(P.FV, fo + fr[d]), ld<CT>(P.FV, fo + fstride + fr[d]), gr, br);
+                    if constexpr (ACC) {
+                        fcl[d].invert_accel(v, dt, eql, ld<CT>(P.FV, fo + fl[d]), ld<CT>(P.FV, fo + fstride + fl[d]), gl, bl);
+                        fcr[d].invert_accel(v, dt, eqr, ld<CT>(P.FV, fo + fr[d]), ld<CT>(P.FV, fo + fstride + fr[d]), gr, br);
+                    } else {
+                        fcl[d].invert(v, eql, ld<CT>(P.FV, fo + fl[d]), ld<CT>(P.FV, fo + fstride + fl[d]), gl, bl);
+                        fcr[d].invert(v, eqr, ld<CT>(P.FV, fo + fr[d]), ld<CT>(P.FV, fo + fstride + fr[d]), gr, br);
+                    }
                     const double sxd = v.xi[d] * P.inv_dx[d];
                     Fg += sxd * (gr - gl);
                     Fb += sxd * (br - bl);
@@ -1084,17 +1149,23 @@ struct UpdateKernel {
                 const double beq1 = (v.hx2 + k1.cRT2) * geq1;
                 const double Z0 = xu0 - k0.hu2;
                 // eq. phiupdate, as in the plain forms
-                const double gn = (g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg) * inv_g;
-                const double bn = (b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
-                                   4.0 * k0.eta * Z0 * (g - geq0)) *
-                                  inv_b;
+                double gn = g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg;
+                double bn = b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
+                            4.0 * k0.eta * Z0 * (g - geq0);
+                if constexpr (ACC) {
+                    const double c0 = 2.0 * dt * k0.inv2RT * (v.ax - au0);
+                    gn += c0 * geq0;
+                    bn += dt * v.ax * (g - geq0) + c0 * beq0;
+                }
+                gn *= inv_g;
+                bn *= inv_b;
                 if (inside) {
                     row_st_stream<ST, H>(P.g_out, off, cc, gn);
                     row_st_stream<ST, H>(P.b_out, off, cc, bn);
                     if constexpr (quarter_stored(D)) {
                         // next step's phi_bar_plus from the state as stored
                         double qg, qb;
-                        quarter_step_eq<D>(k1, v, geq1, row_round<ST, H>(gn), row_round<ST, H>(bn), qg, qb);
+                        quarter_step_eq<D, ACC>(k1, v, geq1, row_round<ST, H>(gn), row_round<ST, H>(bn), qg, qb, &P);
                         row_st_stream<ST, H>(P.qg, off, cc, qg);
                         row_st_stream<ST, H>(P.qb, off, cc, qb);
                     }
@@ -1122,9 +1193,9 @@ template <int D>
 constexpr int face_sum_waves() { return D == 1 ? 4 : (D == 2 ? 3 : 1); }
 
 // The single-problem face-sum kernel of tile shape TID.
-template <int D, typename ST, bool DIR, bool SS, int TID>
+template <int D, typename ST, bool DIR, bool SS, int TID, bool ACC>
 __global__ __launch_bounds__(tile_threads(D, TID), face_sum_waves<D>()) void k_face_sums(Problem P) {
-    using K = FaceSumKernel<D, ST, DIR, SS, TID>;
+    using K = FaceSumKernel<D, ST, DIR, SS, TID, ACC>;
     static_assert(sizeof(typename K::Smem) == face_sum_lds_bytes(D, TID, sizeof(typename K::CT)),
                   "host and kernel LDS sizes differ");
     __shared__ typename K::Smem sm;
@@ -1137,11 +1208,11 @@ __global__ __launch_bounds__(tile_threads(D, TID), face_sum_waves<D>()) void k_f
 // shape, storage form, boundary kind and reconstruction.  Shapes whose boxes
 // do not fit a CU's LDS for the storage form are refused (the host never
 // selects them).
-template <int D, typename ST, bool DIR, bool SS, int TID>
+template <int D, typename ST, bool DIR, bool SS, int TID, bool ACC = false>
 hipError_t launch_face_sums_shape(const Problem& P, hipStream_t s) {
     if constexpr (face_tile_fits(D, TID, sizeof(typename StoreT<ST>::C))) {
         const unsigned nb = (unsigned)(P.tiles1[0] * P.tiles1[1] * P.tiles1[2] * P.nslices);
-        hipLaunchKernelGGL((k_face_sums<D, ST, DIR, SS, TID>), dim3(nb), dim3(tile_threads(D, TID)), 0, s, P);
+        hipLaunchKernelGGL((k_face_sums<D, ST, DIR, SS, TID, ACC>), dim3(nb), dim3(tile_threads(D, TID)), 0, s, P);
         return hipGetLastError();
     } else {
         return hipErrorInvalidConfiguration;
@@ -1152,7 +1223,7 @@ template <int D, typename ST, int TID>
 int face_sum_occupancy_shape() {
     if constexpr (face_tile_fits(D, TID, sizeof(typename StoreT<ST>::C))) {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums<D, ST, false, false, TID>),
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_sums<D, ST, false, false, TID, false>),
                                                         tile_threads(D, TID), 0) != hipSuccess) {
             (void)hipGetLastError();
             return 0;
@@ -1228,6 +1299,12 @@ __device__ void face_close_one(const Problem& P, long long idx) {
     }
     double Wf[5] = {S[0], S[1], D >= 2 ? S[2] : 0.0, D >= 3 ? S[3] : 0.0, 0.0};
     Wf[D + 1] = S[D + 1];
+    if (P.has_accel) {
+        // eqs. rhoubar, rhoEbar: (h/2) rho a and (h/2) (rho u).a, h/2 = dt/4,
+        // with the face momentum just formed
+        for (int e = 0; e < D; ++e) Wf[1 + e] += 0.25 * P.dt * Wf[0] * P.accel[e];
+        for (int e = 0; e < D; ++e) Wf[D + 1] += 0.25 * P.dt * Wf[1 + e] * P.accel[e];
+    }
     Prim q = primitives(P, Wf);
     if (q.bad) {
         raise_error(P.err);
@@ -1242,10 +1319,10 @@ __device__ void face_close_one(const Problem& P, long long idx) {
     const double cRT2 = 0.5 * P.c_int * q.RT;
 
     // separable discrete moments of the face Maxwellian: M[k][p] = sum_m w_m xi_m^p E_k(m)
-    double M[3][4];
+    double M[3][5];
     int off = 0;
     for (int k = 0; k < 3; ++k) {
-        for (int p = 0; p < 4; ++p) M[k][p] = 0.0;
+        for (int p = 0; p < 5; ++p) M[k][p] = 0.0;
         if (k >= D) {
             M[k][0] = 1.0;
             continue;
@@ -1257,6 +1334,7 @@ __device__ void face_close_one(const Problem& P, long long idx) {
             M[k][1] += e * x;
             M[k][2] += e * x * x;
             M[k][3] += e * x * x * x;
+            M[k][4] += e * x * x * x * x;
         }
         off += P.nv[k];
     }
@@ -1285,12 +1363,51 @@ __device__ void face_close_one(const Problem& P, long long idx) {
     const double ig = 1.0 / (1.0 + beta), ib = 1.0 / (1.0 + betab);
     double Gm = (S[1 + d] + beta * E1) * ig;
     double Gp[3];
-    double ZG = -hu2 * Gm;
-    for (int e = 0; e < D; ++e) {
-        Gp[e] = (S[D + 2 + e] + beta * E2[e]) * ig;
-        ZG += q.u[e] * Gp[e];
+    for (int e = 0; e < D; ++e) Gp[e] = (S[D + 2 + e] + beta * E2[e]) * ig;
+    double accE = 0.0;
+    if (P.has_accel) {
+        // The acceleration's (h/2) S terms at the face (eqs. gsource,
+        // bsource with the velocity derivative on the equilibrium) enter g_f
+        // as ig c (a.xi - a.u) g_eq and b_f as ib [(dt/4) a.xi (g_f - g_eq)
+        // + c (a.xi - a.u) b_eq], c = (h/2)/(R T); their flux moments need
+        // third and fourth separable moments of the face Maxwellian.
+        auto mom = [&](const int* p) { return A * M[0][p[0]] * M[1][p[1]] * M[2][p[2]]; };
+        const double c = 0.5 * P.dt * inv2RT;
+        double au = 0.0, aE2 = 0.0;
+        for (int k = 0; k < D; ++k) {
+            au += P.accel[k] * q.u[k];
+            aE2 += P.accel[k] * E2[k];
+        }
+        Gm += ig * c * (aE2 - au * E1);
+        for (int e = 0; e < D; ++e) {
+            double t3 = 0.0;  // sum_k a_k sum_i w_i xi_d xi_e xi_k g_eq
+            for (int k = 0; k < D; ++k) {
+                int p[3] = {0, 0, 0};
+                p[d] += 1;
+                p[e] += 1;
+                p[k] += 1;
+                t3 += P.accel[k] * mom(p);
+            }
+            Gp[e] += ig * c * (t3 - au * E2[e]);
+        }
+        double aB2 = 0.0, aG = 0.0;  // sum_k a_k sum_i w_i xi_d xi_k b_eq; sum_k a_k (G_k - E2_k)
+        for (int k = 0; k < D; ++k) {
+            double q4 = 0.0;
+            for (int m = 0; m < D; ++m) {
+                int p[3] = {0, 0, 0};
+                p[d] += 1;
+                p[k] += 1;
+                p[m] += 2;
+                q4 += mom(p);
+            }
+            aB2 += P.accel[k] * (0.5 * q4 + cRT2 * E2[k]);
+            aG += P.accel[k] * (Gp[k] - E2[k]);
+        }
+        accE = 0.25 * P.dt * aG + c * (aB2 - au * E3);
     }
-    double Ge = (S[2 * D + 2] + betab * E3 + eta * (ZG - EZ)) * ib;
+    double ZG = -hu2 * Gm;
+    for (int e = 0; e < D; ++e) ZG += q.u[e] * Gp[e];
+    double Ge = (S[2 * D + 2] + betab * E3 + eta * (ZG - EZ) + accE) * ib;
 
     double* Go = P.G + (long long)d * (D + 2) * NE + f;
     Go[0] = Gm;
@@ -1324,8 +1441,8 @@ __device__ void cell_close_one(const Problem& P, long long c) {
         r /= P.n[e];
     }
     long long fl = cc[0] + (long long)P.ne[0] * (cc[1] + (long long)P.ne[1] * cc[2]);
-    double Wn[5];
-    for (int k = 0; k < D + 2; ++k) Wn[k] = P.W_in[k * N + c];
+    double Wn[5], W0[5];
+    for (int k = 0; k < D + 2; ++k) W0[k] = Wn[k] = P.W_in[k * N + c];
     for (int d = 0; d < D; ++d) {
         int rc[3] = {cc[0], cc[1], cc[2]};
         rc[d] += 1;
@@ -1334,6 +1451,13 @@ __device__ void cell_close_one(const Problem& P, long long c) {
         const double* Gd = P.G + (long long)d * (D + 2) * NE;
         for (int k = 0; k < D + 2; ++k)
             Wn[k] -= P.dt * P.inv_dx[d] * (Gd[k * NE + fr] - Gd[k * NE + fl]);
+    }
+    if (P.has_accel) {
+        // source integrals at t_n (eqs. rhouupdate, rhoEupdate): rho a, (rho u).a
+        for (int e = 0; e < D; ++e) {
+            Wn[1 + e] += P.dt * W0[0] * P.accel[e];
+            Wn[D + 1] += P.dt * W0[1 + e] * P.accel[e];
+        }
     }
     for (int k = 0; k < D + 2; ++k) P.W_out[k * N + c] = Wn[k];
     Prim q = primitives(P, Wn);

@@ -2,7 +2,9 @@
 // storage form.  The build compiles this file once per dimension
 // (CDG_FACE_DIM = 1, 2, 3), in parallel with the other translation units.
 // Shapes other than the default exist for problems without Dirichlet sides
-// that use the paper's reconstruction; the host selects only those.
+// or external acceleration that use the paper's reconstruction; the host
+// selects only those.  Problems with an external acceleration run the
+// paper's reconstruction only.
 #include "cdugks_device.h"
 
 #ifndef CDG_FACE_DIM
@@ -29,6 +31,12 @@ hipError_t by_shape(const Problem& P, hipStream_t s) {
 
 template <typename ST>
 hipError_t launch_storage(const Problem& P, hipStream_t s) {
+    if (P.has_accel) {
+        // external acceleration: default shape, the paper's reconstruction
+        if (P.tile != 0 || P.recon) return hipErrorInvalidValue;
+        return P.dir_eq ? launch_face_sums_shape<FD, ST, true, false, 0, true>(P, s)
+                        : launch_face_sums_shape<FD, ST, false, false, 0, true>(P, s);
+    }
     if (P.dir_eq || P.recon) {
         if (P.tile != 0) return hipErrorInvalidValue;
         if (P.dir_eq)

@@ -35,6 +35,8 @@ struct Resolved {
     long long pitch, fv_pitch;  // elements between velocity rows (state arrays, face values)
     double dir[3][2][5];  // Dirichlet states (rho, u_x, u_y, u_z, T) per dimension and side
     bool any_dirichlet;
+    double accel[3];      // external acceleration (zero beyond D)
+    bool has_accel;
 };
 
 // Steps per captured graph of a single context.

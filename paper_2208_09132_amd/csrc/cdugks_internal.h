@@ -27,9 +27,10 @@ enum { PF_A = 0, PF_INV2RT, PF_CRT2, PF_IG, PF_BG, PF_IB, PF_BB, PF_EB, PF_HU2, 
 
 // Per-velocity constants ([V][NVEL]): xi, weight, |xi|^2/2, twice the
 // Courant-like numbers, 2 lambda_d = dt xi_d / dx_d (the face value is
-// assembled from half-scale slopes), and the weighted products used by the
-// face sums, w xi_e and w xi_d xi_e ([d][e], 3 x 3).
-enum { VE_XI0 = 0, VE_W = 3, VE_HX2 = 4, VE_LAM0 = 5, VE_WXI0 = 8, VE_WXX = 11, NVEL = 20 };
+// assembled from half-scale slopes), the weighted products used by the
+// face sums, w xi_e and w xi_d xi_e ([d][e], 3 x 3), and a . xi for the
+// external acceleration a.
+enum { VE_XI0 = 0, VE_W = 3, VE_HX2 = 4, VE_LAM0 = 5, VE_WXI0 = 8, VE_WXX = 11, VE_AX = 20, NVEL = 21 };
 
 constexpr int MAX_NSUM = 9;  // 2D+3 face sums for D = 3
 
@@ -82,6 +83,8 @@ struct Problem {
     const long long* rows;
     int recon;    // 0: slopes of slopes (Sec. 2.1), 1: single slope
     int tile;     // face-sum tile shape (index into tile_shape(D, .))
+    int has_accel;     // external acceleration present (a != 0)
+    double accel[3];   // external acceleration a (eqs. gPDE, bPDE)
 };
 
 // One workgroup's assignment in a batched launch.

@@ -98,7 +98,9 @@ __global__ __launch_bounds__(256) void k_init_quarter(Problem P) {
     }
     const double geq = k.A * exp(-c2 * k.inv2RT);
     double qg, qb;
-    quarter_step_eq<D>(k, v, geq, state_ld<ST>(P, P.g_in, (int)i, c), state_ld<ST>(P, P.b_in, (int)i, c), qg, qb);
+    const double g = state_ld<ST>(P, P.g_in, (int)i, c), b = state_ld<ST>(P, P.b_in, (int)i, c);
+    if (P.has_accel) quarter_step_eq<D, true>(k, v, geq, g, b, qg, qb, &P);
+    else quarter_step_eq<D>(k, v, geq, g, b, qg, qb);
     state_st<ST, false>(P, P.qg, (int)i, c, qg);
     state_st<ST, false>(P, P.qb, (int)i, c, qb);
 }
@@ -106,12 +108,12 @@ __global__ __launch_bounds__(256) void k_init_quarter(Problem P) {
 
 
 // update grid: blocks of 256 consecutive cells x velocity slices
-template <int D, typename ST>
+template <int D, typename ST, bool ACC = false>
 __global__ __launch_bounds__(WG, 2) void k_update(Problem P) {
     const int nblk = (int)((P.N + WG - 1) / WG);
     int q = xcd_remap(blockIdx.x, gridDim.x);
     int blk = q % nblk, slice = q / nblk;
-    UpdateKernel<D, ST>::run(P, (long long)blk * WG + threadIdx.x, slice, P.nslices_upd);
+    UpdateKernel<D, ST, ACC>::run(P, (long long)blk * WG + threadIdx.x, slice, P.nslices_upd);
 }
 
 template <typename ST, int MAXD>
@@ -239,9 +241,15 @@ int face_sum_blocks_per_cu(int D, int storage, int tile) {
 
 hipError_t launch_update(const Problem& P, hipStream_t s) {
     unsigned nb = (unsigned)(((P.N + WG - 1) / WG) * P.nslices_upd);
-#define CDG_L(DD, TT) hipLaunchKernelGGL((k_update<DD, TT>), dim3(nb), dim3(WG), 0, s, P)
-    CDG_DISPATCH(P.storage, P.D, CDG_L);
+    if (P.has_accel) {
+#define CDG_L(DD, TT) hipLaunchKernelGGL((k_update<DD, TT, true>), dim3(nb), dim3(WG), 0, s, P)
+        CDG_DISPATCH(P.storage, P.D, CDG_L);
 #undef CDG_L
+    } else {
+#define CDG_L(DD, TT) hipLaunchKernelGGL((k_update<DD, TT>), dim3(nb), dim3(WG), 0, s, P)
+        CDG_DISPATCH(P.storage, P.D, CDG_L);
+#undef CDG_L
+    }
     return hipGetLastError();
 }
 

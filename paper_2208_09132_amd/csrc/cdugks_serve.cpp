@@ -202,6 +202,8 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
         if (!ctxs[j]) return fail(CDUGKS_ERR_INVALID, "null context in batch");
         if (ctxs[j]->in_batch) return fail(CDUGKS_ERR_BUSY, "context already belongs to a batch");
         if (ctxs[j]->sticky) return fail(ctxs[j]->sticky, "context is in an error state");
+        if (ctxs[j]->r.has_accel)
+            return fail(CDUGKS_ERR_INVALID, "contexts with an external acceleration run alone, not in batches");
         for (int k = 0; k < j; ++k)
             if (ctxs[k] == ctxs[j]) return fail(CDUGKS_ERR_INVALID, "context listed twice");
     }
@@ -611,6 +613,8 @@ int cdugks_submit(cdugks_server* s, const cdugks_space* space, const cdugks_velo
     if (rc) return rc;
     if (r.bytes > s->budget)
         return fail(CDUGKS_ERR_TOO_LARGE, "request needs %zu bytes, budget is %zu", r.bytes, s->budget);
+    if (r.has_accel)
+        return fail(CDUGKS_ERR_INVALID, "requests with an external acceleration are not served (run them alone)");
     for (long long c = 0; c < r.N; ++c)
         if (!(rho[c] > 0.0) || !(T[c] > 0.0) || !std::isfinite(rho[c]) || !std::isfinite(T[c]))
             return fail(CDUGKS_ERR_INVALID, "non-physical initial moments at cell %lld", c);
@@ -685,6 +689,8 @@ void cdugks_server_destroy(cdugks_server* s) {
 int cdugks_autotune(cdugks_ctx* c, int steps_per_trial) {
     if (!c || steps_per_trial <= 0) return fail(CDUGKS_ERR_INVALID, "bad argument");
     if (c->in_batch) return fail(CDUGKS_ERR_BUSY, "context belongs to a batch");
+    if (c->r.has_accel)
+        return fail(CDUGKS_ERR_INVALID, "autotuning times batched launches, which exclude an external acceleration");
     if (c->sticky) return fail(c->sticky, "context is in an error state");
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

@@ -145,3 +145,15 @@ def test_destroying_a_batched_context_is_refused():
         assert np.array_equal(x, y)
     a.close()
     b.close()
+
+
+def test_acceleration_validation():
+    p = wl.sod(n=16, nv=10)
+    for bad in ([math.nan], [math.inf]):
+        with pytest.raises(cd.CdugksError) as ei:
+            cd.cdugks_required_bytes(dict(p, accel=bad))
+        assert ei.value.code == cd.ERR_INVALID
+    with pytest.raises(cd.CdugksError) as ei:
+        cd.cdugks_required_bytes(dict(p, accel=[1.0], reconstruction="single_slope"))
+    assert "reconstruction" in str(ei.value)
+    assert cd.cdugks_required_bytes(dict(p, accel=[1.0])) > 0
