@@ -192,42 +192,33 @@ __device__ __forceinline__ double slot_value(typename StoreT<ST>::R r, unsigned 
     else return (double)r;
 }
 
-// Access within one velocity row whose kind is known at compile time: `off`
-// is the element offset i N of the row (double, float) or its byte offset
-// (Bf16Tail, H: the row holds BF16).
-template <typename ST, bool H>
-__device__ __forceinline__ double row_ld(const void* base, long long off, long long c) {
-    if constexpr (StoreT<ST>::MIXED) {
-        const char* row = (const char*)base + off;
-        if constexpr (H) return (double)(float)((const __bf16*)row)[c];
-        else return (double)((const float*)row)[c];
-    } else {
-        return (double)((const ST*)base)[off + c];
+// Access within one velocity row of the update kernel, whose element kind is
+// known at compile time: double or float rows, or the BF16 rows of the
+// BF16-tail form (Bf16Row).  `off` is the row's byte offset in the array.
+// Stores are non-temporal (the kernel never reads them back); round() gives
+// the value as it will be stored.
+struct Bf16Row {};
+template <typename E>
+struct RowIO {
+    __device__ static double ld(const void* base, long long off, long long c) {
+        return (double)((const E*)((const char*)base + off))[c];
     }
-}
-template <typename ST, bool H>
-__device__ __forceinline__ double row_round(double v) {
-    if constexpr (StoreT<ST>::MIXED) {
-        if constexpr (H) return (double)(float)(__bf16)(float)v;
-        else return (double)(float)v;
-    } else {
-        return (double)(ST)v;
+    __device__ static void st(void* base, long long off, long long c, double v) {
+        __builtin_nontemporal_store((E)v, (E*)((char*)base + off) + c);
     }
-}
-template <typename ST, bool H>
-__device__ __forceinline__ void row_st_stream(void* base, long long off, long long c, double v) {
-    if constexpr (StoreT<ST>::MIXED) {
-        char* row = (char*)base + off;
-        if constexpr (H) {
-            const unsigned short h = __builtin_bit_cast(unsigned short, (__bf16)(float)v);
-            __builtin_nontemporal_store(h, (unsigned short*)row + c);
-        } else {
-            __builtin_nontemporal_store((float)v, (float*)row + c);
-        }
-    } else {
-        st_stream<ST>(base, off + c, v);
+    __device__ static double round(double v) { return (double)(E)v; }
+};
+template <>
+struct RowIO<Bf16Row> {
+    __device__ static double ld(const void* base, long long off, long long c) {
+        return (double)(float)((const __bf16*)((const char*)base + off))[c];
     }
-}
+    __device__ static void st(void* base, long long off, long long c, double v) {
+        const unsigned short h = __builtin_bit_cast(unsigned short, (__bf16)(float)v);
+        __builtin_nontemporal_store(h, (unsigned short*)((char*)base + off) + c);
+    }
+    __device__ static double round(double v) { return (double)(float)(__bf16)(float)v; }
+};
 
 // ---------------------------------------------------------------------------
 // primitives shared by the per-cell and per-face closures (Sec. 2)
@@ -417,42 +408,25 @@ __device__ __forceinline__ CT face_value_single(CT qU, const CT* haU, int d, CT 
     return val;
 }
 
-// Face coefficients used to invert eq. phibar at a face: NFC per face.
+// Face coefficients used to invert eq. phibar at a face.  The inversion
+// g = ig gbar + bg g_eq with bg = 1 - ig is evaluated as g_eq + ig (gbar -
+// g_eq) (likewise b with ib), so bg and bb need no registers.
 template <int D>
 struct FaceCoef {
-    static constexpr int NFC = 9 + D;
-    double A, inv2RT, cRT2, ig, bg, ib, bb, eb, hu2, u[D];
+    double A, inv2RT, cRT2, ig, ib, eb, hu2, u[D];
     __device__ void load(const double* F, long long NE) {
         A = F[PF_A * NE];
         inv2RT = F[PF_INV2RT * NE];
         cRT2 = F[PF_CRT2 * NE];
         ig = F[PF_IG * NE];
-        bg = F[PF_BG * NE];
         ib = F[PF_IB * NE];
-        bb = F[PF_BB * NE];
         eb = F[PF_EB * NE];
         hu2 = F[PF_HU2 * NE];
 #pragma unroll
         for (int e = 0; e < D; ++e) u[e] = F[(PF_U0 + e) * NE];
     }
-    // LDS layout [NFC][stride]
-    __device__ void store(double* s, int j, int stride) const {
-        s[0 * stride + j] = A; s[1 * stride + j] = inv2RT; s[2 * stride + j] = cRT2;
-        s[3 * stride + j] = ig; s[4 * stride + j] = bg; s[5 * stride + j] = ib;
-        s[6 * stride + j] = bb; s[7 * stride + j] = eb; s[8 * stride + j] = hu2;
-#pragma unroll
-        for (int e = 0; e < D; ++e) s[(9 + e) * stride + j] = u[e];
-    }
-    __device__ void fetch(const double* s, int j, int stride) {
-        A = s[0 * stride + j]; inv2RT = s[1 * stride + j]; cRT2 = s[2 * stride + j];
-        ig = s[3 * stride + j]; bg = s[4 * stride + j]; ib = s[5 * stride + j];
-        bb = s[6 * stride + j]; eb = s[7 * stride + j]; hu2 = s[8 * stride + j];
-#pragma unroll
-        for (int e = 0; e < D; ++e) u[e] = s[(9 + e) * stride + j];
-    }
-    // phi at the face from phi_bar: g = ig gbar + bg g_eq; b likewise with the
-    // S_b source at the face evaluated with the face g.
-
+    // phi at the face from phi_bar (eq. phibar inverted): g first, then b with
+    // the S_b source at the face evaluated with the face g.
     __device__ __forceinline__ void invert(const Vel& v, double geq, double vg, double vb, double& gF,
                                            double& bF) const {
         double xu = 0.0;
@@ -460,8 +434,8 @@ struct FaceCoef {
         for (int e = 0; e < D; ++e) xu += v.xi[e] * u[e];
         double beq = (v.hx2 + cRT2) * geq;
         double Z = xu - hu2;
-        gF = ig * vg + bg * geq;
-        bF = ib * vb + bb * beq + eb * Z * (gF - geq);
+        gF = geq + ig * (vg - geq);
+        bF = beq + ib * (vb - beq) + eb * Z * (gF - geq);
     }
     // The same with an external acceleration a: the face's (h/2) S terms
     // (eqs. gsource, bsource, velocity derivative on the equilibrium), with
@@ -481,8 +455,8 @@ struct FaceCoef {
         double beq = (v.hx2 + cRT2) * geq;
         double Z = xu - hu2;
         const double c = c2 * (v.ax - au);
-        gF = ig * vg + bg * geq + ig * c * geq;
-        bF = ib * vb + bb * beq + eb * Z * (gF - geq) + ib * (0.25 * dt * v.ax * (gF - geq) + c * beq);
+        gF = geq + ig * (vg - geq + c * geq);
+        bF = beq + ib * (vb - beq + 0.25 * dt * v.ax * (gF - geq) + c * beq) + eb * Z * (gF - geq);
     }
 };
 
@@ -946,7 +920,11 @@ struct FaceSumKernel {
 // ACC: the problem has an external acceleration (face inversion, the cell
 // source of eq. phiupdate and, in 3-D, the next quarter-step fields carry
 // its terms).
-template <int D, typename ST, bool ACC = false>
+// ROWS (BF16-tail form only): 0 updates every velocity row of the slice,
+// 1 only its FP32 rows, 2 only its BF16 rows.  The 3-D single-problem step
+// runs the two row kinds as two launches, so that each holds one loop body
+// (see launch_update).
+template <int D, typename ST, bool ACC = false, int ROWS = 0>
 struct UpdateKernel {
     using CT = typename StoreT<ST>::C;  // stored face values
     __device__ static void run(const Problem& P, long long c, int slice, int nslices) {
@@ -1019,169 +997,121 @@ struct UpdateKernel {
         }
         int ix = v0 % nvx;
 
+        // One velocity of the slice; its rows (g, b in and out, and the 3-D
+        // quarter-step fields) hold elements of kind E and start `off` bytes
+        // into each state array.  Every storage form runs this one body.
+        auto velocity = [&](int i, long long off, auto kind) __attribute__((always_inline)) {
+            using IO = RowIO<decltype(kind)>;
+            const Vel v = load_vel(P.vel, i);
+            if constexpr (WALKER) {
+                if (i == v0 || ix % WALK == 0) {
+                    const int a0 = ix - ix % WALK;
+                    // a slice starting inside a block walks from its anchor
+                    const Vel va = a0 == ix ? v : load_vel(P.vel, i - (ix - a0));
+                    w0.anchor<D>(k0.A, k0.inv2RT, k0.u, va, h);
+                    w1.anchor<D>(k1.A, k1.inv2RT, k1.u, va, h);
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        wl[d].template anchor<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, va, h);
+                        wr[d].template anchor<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, va, h);
+                    }
+                    for (int j = a0; j < ix; ++j) {
+                        w0.advance();
+                        w1.advance();
+#pragma unroll
+                        for (int d = 0; d < D; ++d) {
+                            wl[d].advance();
+                            wr[d].advance();
+                        }
+                    }
+                }
+            }
+            const double g = IO::ld(P.g_in, off, cc);
+            const double b = IO::ld(P.b_in, off, cc);
+            double Fg = 0.0, Fb = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const long long o = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch;
+                const double eql = WALKER ? wl[d].template value<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v)
+                                          : maxwellian<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v);
+                const double eqr = WALKER ? wr[d].template value<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v)
+                                          : maxwellian<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v);
+                double gl, bl, gr, br;
+                if constexpr (ACC) {
+                    fcl[d].invert_accel(v, dt, eql, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl, bl);
+                    fcr[d].invert_accel(v, dt, eqr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr, br);
+                } else {
+                    fcl[d].invert(v, eql, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl, bl);
+                    fcr[d].invert(v, eqr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr, br);
+                }
+                const double sxd = v.xi[d] * P.inv_dx[d];
+                Fg += sxd * (gr - gl);
+                Fb += sxd * (br - bl);
+            }
+            double xu0 = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; ++d) xu0 += v.xi[d] * k0.u[d];
+            const double geq0 = WALKER ? w0.value<D>(k0.A, k0.inv2RT, k0.u, v) : maxwellian<D>(k0.A, k0.inv2RT, k0.u, v);
+            const double beq0 = (v.hx2 + k0.cRT2) * geq0;
+            const double geq1 = WALKER ? w1.value<D>(k1.A, k1.inv2RT, k1.u, v) : maxwellian<D>(k1.A, k1.inv2RT, k1.u, v);
+            const double beq1 = (v.hx2 + k1.cRT2) * geq1;
+            const double Z0 = xu0 - k0.hu2;
+            // eq. phiupdate with dt/(2 tau) = 2 beta and dt S_b = 4 eta Z (g - g_eq)
+            double gn = g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg;
+            double bn = b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
+                        4.0 * k0.eta * Z0 * (g - geq0);
+            if constexpr (ACC) {
+                const double c0 = 2.0 * dt * k0.inv2RT * (v.ax - au0);
+                gn += c0 * geq0;
+                bn += dt * v.ax * (g - geq0) + c0 * beq0;
+            }
+            gn *= inv_g;
+            bn *= inv_b;
+            if (inside) {
+                IO::st(P.g_out, off, cc, gn);
+                IO::st(P.b_out, off, cc, bn);
+                if constexpr (quarter_stored(D)) {
+                    // next step's phi_bar_plus from the state as stored
+                    double qg, qb;
+                    quarter_step_eq<D, ACC>(k1, v, geq1, IO::round(gn), IO::round(bn), qg, qb, &P);
+                    IO::st(P.qg, off, cc, qg);
+                    IO::st(P.qb, off, cc, qb);
+                }
+            }
+            if constexpr (WALKER) {
+                w0.advance();
+                w1.advance();
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    wl[d].advance();
+                    wr[d].advance();
+                }
+                if (++ix == nvx) ix = 0;
+            }
+        };
+
         if constexpr (!StoreT<ST>::MIXED) {
             // FP64 without the recurrence: two velocities per trip (twice the
             // loads in flight per wave)
             constexpr int UNROLL = std::is_same<ST, double>::value && !WALKER ? 2 : 1;
-    #pragma unroll UNROLL
-            for (int i = v0; i < v1; ++i) {
-                const Vel v = load_vel(P.vel, i);
-                if constexpr (WALKER) {
-                    if (i == v0 || ix % WALK == 0) {
-                        const int a0 = ix - ix % WALK;
-                        // a slice starting inside a block walks from its anchor
-                        const Vel va = a0 == ix ? v : load_vel(P.vel, i - (ix - a0));
-                        w0.anchor<D>(k0.A, k0.inv2RT, k0.u, va, h);
-                        w1.anchor<D>(k1.A, k1.inv2RT, k1.u, va, h);
-    #pragma unroll
-                        for (int d = 0; d < D; ++d) {
-                            wl[d].template anchor<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, va, h);
-                            wr[d].template anchor<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, va, h);
-                        }
-                        for (int j = a0; j < ix; ++j) {
-                            w0.advance();
-                            w1.advance();
-    #pragma unroll
-                            for (int d = 0; d < D; ++d) {
-                                wl[d].advance();
-                                wr[d].advance();
-                            }
-                        }
-                    }
-                }
-                const long long vb = (long long)i * P.pitch;
-                const double g = ld<ST>(P.g_in, vb + cc);
-                const double b = ld<ST>(P.b_in, vb + cc);
-                double Fg = 0.0, Fb = 0.0;
-    #pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const long long o = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch;
-                    const double eql = WALKER ? wl[d].template value<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v)
-                                              : maxwellian<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v);
-                    const double eqr = WALKER ? wr[d].template value<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v)
-                                              : maxwellian<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v);
-                    double gl, bl, gr, br;
-                    if constexpr (ACC) {
-                        fcl[d].invert_accel(v, dt, eql, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl, bl);
-                        fcr[d].invert_accel(v, dt, eqr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr, br);
-                    } else {
-                        fcl[d].invert(v, eql, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl, bl);
-                        fcr[d].invert(v, eqr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr, br);
-                    }
-                    const double sxd = v.xi[d] * P.inv_dx[d];
-                    Fg += sxd * (gr - gl);
-                    Fb += sxd * (br - bl);
-                }
-                double xu0 = 0.0;
-    #pragma unroll
-                for (int d = 0; d < D; ++d) xu0 += v.xi[d] * k0.u[d];
-                const double geq0 = WALKER ? w0.value<D>(k0.A, k0.inv2RT, k0.u, v) : maxwellian<D>(k0.A, k0.inv2RT, k0.u, v);
-                const double beq0 = (v.hx2 + k0.cRT2) * geq0;
-                const double geq1 = WALKER ? w1.value<D>(k1.A, k1.inv2RT, k1.u, v) : maxwellian<D>(k1.A, k1.inv2RT, k1.u, v);
-                const double beq1 = (v.hx2 + k1.cRT2) * geq1;
-                const double Z0 = xu0 - k0.hu2;
-                // eq. phiupdate with dt/(2 tau) = 2 beta and dt S_b = 4 eta Z (g - g_eq)
-                double gn = g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg;
-                double bn = b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
-                            4.0 * k0.eta * Z0 * (g - geq0);
-                if constexpr (ACC) {
-                    const double c0 = 2.0 * dt * k0.inv2RT * (v.ax - au0);
-                    gn += c0 * geq0;
-                    bn += dt * v.ax * (g - geq0) + c0 * beq0;
-                }
-                gn *= inv_g;
-                bn *= inv_b;
-                if (inside) {
-                    st_stream<ST>(P.g_out, vb + cc, gn);
-                    st_stream<ST>(P.b_out, vb + cc, bn);
-                    if constexpr (quarter_stored(D)) {
-                        // next step's phi_bar_plus from the state as stored
-                        double qg, qb;
-                        quarter_step_eq<D, ACC>(k1, v, geq1, (double)(ST)gn, (double)(ST)bn, qg, qb, &P);
-                        st_stream<ST>(P.qg, vb + cc, qg);
-                        st_stream<ST>(P.qb, vb + cc, qb);
-                    }
-                }
-                if constexpr (WALKER) {
-                    w0.advance();
-                    w1.advance();
-    #pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        wl[d].advance();
-                        wr[d].advance();
-                    }
-                    if (++ix == nvx) ix = 0;
-                }
-            }
+#pragma unroll UNROLL
+            for (int i = v0; i < v1; ++i) velocity(i, (long long)i * P.pitch * (long long)sizeof(ST), ST{});
         } else {
-            // BF16-tail form: the row kind is uniform, so each velocity runs a
-            // copy of the body specialised for FP32 or BF16 rows; no
-            // recurrence for the equilibria
-            auto one = [&](int i, long long off, auto half) __attribute__((always_inline)) {
-                constexpr bool H = decltype(half)::value;
-                const Vel v = load_vel(P.vel, i);
-                const double g = row_ld<ST, H>(P.g_in, off, cc);
-                const double b = row_ld<ST, H>(P.b_in, off, cc);
-                double Fg = 0.0, Fb = 0.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const long long fo = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch;
-                    const double eql = maxwellian<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v);
-                    const double eqr = maxwellian<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v);
-                    double gl, bl, gr, br;
-                    if constexpr (ACC) {
-                        fcl[d].invert_accel(v, dt, eql, ld<CT>(P.FV, fo + fl[d]), ld<CT>(P.FV, fo + fstride + fl[d]), gl, bl);
-                        fcr[d].invert_accel(v, dt, eqr, ld<CT>(P.FV, fo + fr[d]), ld<CT>(P.FV, fo + fstride + fr[d]), gr, br);
-                    } else {
-                        fcl[d].invert(v, eql, ld<CT>(P.FV, fo + fl[d]), ld<CT>(P.FV, fo + fstride + fl[d]), gl, bl);
-                        fcr[d].invert(v, eqr, ld<CT>(P.FV, fo + fr[d]), ld<CT>(P.FV, fo + fstride + fr[d]), gr, br);
-                    }
-                    const double sxd = v.xi[d] * P.inv_dx[d];
-                    Fg += sxd * (gr - gl);
-                    Fb += sxd * (br - bl);
+            // BF16-tail form: the row kind is uniform, so each velocity runs
+            // the body for FP32 or BF16 rows; the FP32 rows of the slice
+            // first, then its BF16 rows (every (cell, velocity) is updated on
+            // its own, so the order is free); no recurrence for the equilibria
+            if constexpr (ROWS != 2) {
+                for (int i = v0; i < v1; ++i) {
+                    const long long o = row_word(P, i);
+                    if (!(o & 1)) velocity(i, o, float{});
                 }
-                double xu0 = 0.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) xu0 += v.xi[d] * k0.u[d];
-                const double geq0 = maxwellian<D>(k0.A, k0.inv2RT, k0.u, v);
-                const double beq0 = (v.hx2 + k0.cRT2) * geq0;
-                const double geq1 = maxwellian<D>(k1.A, k1.inv2RT, k1.u, v);
-                const double beq1 = (v.hx2 + k1.cRT2) * geq1;
-                const double Z0 = xu0 - k0.hu2;
-                // eq. phiupdate, as in the plain forms
-                double gn = g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg;
-                double bn = b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
-                            4.0 * k0.eta * Z0 * (g - geq0);
-                if constexpr (ACC) {
-                    const double c0 = 2.0 * dt * k0.inv2RT * (v.ax - au0);
-                    gn += c0 * geq0;
-                    bn += dt * v.ax * (g - geq0) + c0 * beq0;
-                }
-                gn *= inv_g;
-                bn *= inv_b;
-                if (inside) {
-                    row_st_stream<ST, H>(P.g_out, off, cc, gn);
-                    row_st_stream<ST, H>(P.b_out, off, cc, bn);
-                    if constexpr (quarter_stored(D)) {
-                        // next step's phi_bar_plus from the state as stored
-                        double qg, qb;
-                        quarter_step_eq<D, ACC>(k1, v, geq1, row_round<ST, H>(gn), row_round<ST, H>(bn), qg, qb, &P);
-                        row_st_stream<ST, H>(P.qg, off, cc, qg);
-                        row_st_stream<ST, H>(P.qb, off, cc, qb);
-                    }
-                }
-            };
-            // the FP32 rows of the slice, then its BF16 rows (every (cell,
-            // velocity) is updated on its own, so the order is free): each
-            // loop holds one straight-line body and the register budget of
-            // the FP32 form
-            for (int i = v0; i < v1; ++i) {
-                const long long o = row_word(P, i);
-                if (!(o & 1)) one(i, o, std::false_type{});
             }
-            for (int i = v0; i < v1; ++i) {
-                const long long o = row_word(P, i);
-                if (o & 1) one(i, o & ~1LL, std::true_type{});
+            if constexpr (ROWS != 1) {
+                for (int i = v0; i < v1; ++i) {
+                    const long long o = row_word(P, i);
+                    if (o & 1) velocity(i, o & ~1LL, Bf16Row{});
+                }
             }
         }
     }
@@ -1419,9 +1349,7 @@ __device__ void face_close_one(const Problem& P, long long idx) {
     F[PF_INV2RT * NE] = inv2RT;
     F[PF_CRT2 * NE] = cRT2;
     F[PF_IG * NE] = ig;
-    F[PF_BG * NE] = beta * ig;
     F[PF_IB * NE] = ib;
-    F[PF_BB * NE] = betab * ib;
     F[PF_EB * NE] = eta * ib;
     F[PF_HU2 * NE] = hu2;
     for (int e = 0; e < 3; ++e) F[(PF_U0 + e) * NE] = q.u[e];

@@ -20,10 +20,9 @@ enum { PC_A = 0, PC_INV2RT, PC_CRT2, PC_BETA, PC_BETAB, PC_ETA, PC_HU2, PC_U0, N
 
 // Per-face coefficient set ([D][NFP][NE]), computed from the face W:
 //   A, INV2RT, CRT2, HU2, U0..U2 as above at the face, plus the inversion of
-//   eq. phibar:  g = IG * gbar + BG * g_eq,
-//                b = IB * bbar + BB * b_eq + EB * Z * (g - g_eq)
-enum { PF_A = 0, PF_INV2RT, PF_CRT2, PF_IG, PF_BG, PF_IB, PF_BB, PF_EB, PF_HU2, PF_U0,
-       NFP = PF_U0 + 3 };
+//   eq. phibar:  g = g_eq + IG (gbar - g_eq),
+//                b = b_eq + IB (bbar - b_eq) + EB * Z * (g - g_eq)
+enum { PF_A = 0, PF_INV2RT, PF_CRT2, PF_IG, PF_IB, PF_EB, PF_HU2, PF_U0, NFP = PF_U0 + 3 };
 
 // Per-velocity constants ([V][NVEL]): xi, weight, |xi|^2/2, twice the
 // Courant-like numbers, 2 lambda_d = dt xi_d / dx_d (the face value is
