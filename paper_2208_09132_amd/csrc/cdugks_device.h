@@ -815,42 +815,51 @@ struct FaceSumKernel {
                 const int a_m = G::aidx(tx - dxo, ty - dyo, tz - dzo);
                 const int a_mm = G::aidx(tx - 2 * dxo, ty - 2 * dyo, tz - 2 * dzo);
                 const int a_p = G::aidx(tx + dxo, ty + dyo, tz + dzo);
-                CT fv[2];
-#pragma unroll
-                for (int f = 0; f < 2; ++f) {
+                // Upwind side by the sign of xi_d, which is uniform across the
+                // workgroup: tested on its bits with scalar integer
+                // instructions, so each velocity takes one branch (the mean
+                // of both one-sided values only for xi_d = 0).
+                const long long xbits = __builtin_bit_cast(long long, xd);
+                const bool from_left = xbits > 0;                               // xi_d > 0
+                const bool from_right = xbits < 0 && (xbits << 1) != 0;          // xi_d < 0
+                // the face value from the upwind cell c - d (left) or c (right)
+                auto left_value = [&](int f) __attribute__((always_inline)) {
                     const CT* sq = f == 0 ? sq0 : sq1;
                     const CT* sa = f == 0 ? sa0 : sa1;
                     CT aU[D], aL[D], aR[D];
-                    CT left = 0, right = 0;
-                    if constexpr (SS) {
-                        if (xd >= 0.0) {  // upwind c - d
 #pragma unroll
-                            for (int e = 0; e < D; ++e) aU[e] = sa[e * G::NA + a_m];
-                            left = face_value_single<D, CT>(sq[q_m], aU, d, CT(1), v);
-                        }
-                        if (xd <= 0.0)  // upwind c
-                            right = face_value_single<D, CT>(q_own[f], a_own[f], d, CT(-1), v);
-                    } else {
-                        if (xd >= 0.0) {  // upwind c - d: its left and right neighbours are c - 2d and c
+                    for (int e = 0; e < D; ++e) aU[e] = sa[e * G::NA + a_m];
+                    if constexpr (SS) return face_value_single<D, CT>(sq[q_m], aU, d, CT(1), v);
+                    // upwind c - d: its left and right neighbours are c - 2d and c
 #pragma unroll
-                            for (int e = 0; e < D; ++e) {
-                                aU[e] = sa[e * G::NA + a_m];
-                                aL[e] = sa[e * G::NA + a_mm];
-                                aR[e] = a_own[f][e];
-                            }
-                            left = face_value_at<D, CT>(sq[q_m], aU, aL, aR, d, CT(1), v);
-                        }
-                        if (xd <= 0.0) {  // upwind c: neighbours c - d and c + d
-#pragma unroll
-                            for (int e = 0; e < D; ++e) {
-                                aU[e] = a_own[f][e];
-                                aL[e] = sa[e * G::NA + a_m];
-                                aR[e] = sa[e * G::NA + a_p];
-                            }
-                            right = face_value_at<D, CT>(q_own[f], aU, aL, aR, d, CT(-1), v);
-                        }
+                    for (int e = 0; e < D; ++e) {
+                        aL[e] = sa[e * G::NA + a_mm];
+                        aR[e] = a_own[f][e];
                     }
-                    fv[f] = xd > 0.0 ? left : (xd < 0.0 ? right : CT(0.5) * (left + right));
+                    return face_value_at<D, CT>(sq[q_m], aU, aL, aR, d, CT(1), v);
+                };
+                auto right_value = [&](int f) __attribute__((always_inline)) {
+                    const CT* sa = f == 0 ? sa0 : sa1;
+                    if constexpr (SS) return face_value_single<D, CT>(q_own[f], a_own[f], d, CT(-1), v);
+                    // upwind c: neighbours c - d and c + d
+                    CT aL[D], aR[D];
+#pragma unroll
+                    for (int e = 0; e < D; ++e) {
+                        aL[e] = sa[e * G::NA + a_m];
+                        aR[e] = sa[e * G::NA + a_p];
+                    }
+                    return face_value_at<D, CT>(q_own[f], a_own[f], aL, aR, d, CT(-1), v);
+                };
+                CT fv[2];
+                if (from_left) {
+                    fv[0] = left_value(0);
+                    fv[1] = left_value(1);
+                } else if (from_right) {
+                    fv[0] = right_value(0);
+                    fv[1] = right_value(1);
+                } else {
+                    fv[0] = CT(0.5) * (left_value(0) + right_value(0));
+                    fv[1] = CT(0.5) * (left_value(1) + right_value(1));
                 }
                 const double vg = fv[0], vb2 = fv[1];
                 if (fvalid[d]) {
