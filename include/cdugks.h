@@ -123,18 +123,25 @@ typedef struct {
     int velocity_slices;    /* velocity-loop split across workgroups; 0 = auto */
     int reconstruction;     /* CDUGKS_RECON_* */
     int face_tile;          /* face-sum tile shape: 0 = automatic (the autotuner's
-                               choice for the problem's class, else the default);
-                               k >= 1 = the k-th shape of the dimension's list,
-                               cells along (x, y, z) per workgroup:
+                               choice for the problem's class, else the default:
+                               the first shape in 1-D and 2-D, the 16x16 column
+                               in 3-D); k >= 1 = the k-th shape of the
+                               dimension's list, cells along (x, y, z) per
+                               workgroup:
                                  dim 1: 256
                                  dim 2: 16x16, 32x8, 8x32, 32x24
-                                 dim 3: 16x4x4, 32x4x2, 64x2x2, 32x6x4, 64x4x3, 16x8x6
-                               Shapes other than the first need the paper's
-                               reconstruction, no Dirichlet side, and boxes that
-                               fit a CU's LDS in the storage form (the 768-cell
-                               64-wide 3-D shape does not in FP64); else
-                               CDUGKS_ERR_INVALID.  Every shape gives bitwise the
-                               same result. */
+                                 dim 3: 16x4x4, 32x4x2, 64x2x2, 32x6x4, 64x4x3, 16x8x6,
+                                        16x16xZ, 32x8xZ, 32x16xZ
+                               (xZ: a column that walks the whole z extent for
+                               one velocity, storing the face values, followed by
+                               a kernel that sums them over velocities).  The
+                               first shape and the default take every problem;
+                               the others need the paper's reconstruction, no
+                               Dirichlet side and no acceleration, and all need
+                               their staged planes or boxes to fit a CU's LDS in
+                               the storage form (the 768-cell 64-wide 3-D box
+                               does not in FP64); else CDUGKS_ERR_INVALID.
+                               Every shape gives bitwise the same result. */
     double accel[3];        /* external acceleration a (e.g. gravity; Sec. 2,
                                eqs. gPDE, bPDE), components >= dim ignored; all
                                zero = none.  The sources of eqs. gsource and

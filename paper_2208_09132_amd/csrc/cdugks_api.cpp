@@ -256,8 +256,10 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
                         "reconstruction option)",
                         pa->face_tile);
         set_face_tile(r, pa->face_tile - 1);
-    } else if (int tt = tuned_face_tile(r); tt > 0 && face_tile_usable(r, tt)) {
+    } else if (int tt = tuned_face_tile(r); tt >= 0 && face_tile_usable(r, tt)) {
         set_face_tile(r, tt);
+    } else if (face_tile_usable(r, default_face_tile(D))) {
+        set_face_tile(r, default_face_tile(D));
     }
 
     // byte plan
@@ -312,7 +314,8 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
 
 void set_face_tile(Resolved& r, int tile) {
     const TileExt t = tile_shape(r.D, tile);
-    const int te[3] = {t.x, t.y, t.z};
+    // a z-marching column spans the face grid along z
+    const int te[3] = {t.x, t.y, tile_zmarch(r.D, tile) ? r.ne[2] : t.z};
     r.tile = tile;
     for (int d = 0; d < 3; ++d) r.tiles1[d] = (r.ne[d] + te[d] - 1) / te[d];
 }
@@ -320,7 +323,12 @@ void set_face_tile(Resolved& r, int tile) {
 bool face_tile_usable(const Resolved& r, int tile) {
     if (tile < 0 || tile >= tile_shape_count(r.D)) return false;
     if (tile == 0) return true;
-    if (r.any_dirichlet || r.recon != CDUGKS_RECON_SLOPES_OF_SLOPES || r.has_accel) return false;
+    // shape 0 and the default shape take every problem, the others only those
+    // without Dirichlet sides or acceleration that use the paper's
+    // reconstruction
+    if (tile != default_face_tile(r.D) &&
+        (r.any_dirichlet || r.recon != CDUGKS_RECON_SLOPES_OF_SLOPES || r.has_accel))
+        return false;
     if (!face_tile_fits(r.D, tile, r.storage == CDUGKS_STORE_F64 ? 8 : 4)) return false;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {

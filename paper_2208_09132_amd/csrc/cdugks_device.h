@@ -1173,6 +1173,336 @@ int face_sum_occupancy_shape() {
     }
 }
 
+// ---------------------------------------------------------------------------
+// 3-D face values by z-march (the tile shapes with z = 0).  A workgroup owns a
+// TX x TY column of the face grid for one velocity i and walks it along z.
+// Step z stages the quarter-step fields of plane z+2 (with the xy halo,
+// offsets -3..T+1), forms the limited differences of plane z+1 (all three
+// components, offsets -2..T) and reconstructs the three left faces of its
+// cells in plane z with the box kernel's operands and operations, so the face
+// values are bitwise those of the box kernel.  LDS holds the q planes
+// z-1..z+2 in a ring of four and the differences of planes z and z+1 in a
+// ring of two; the own column's differences of planes z-2 and z-1 and its q
+// of plane z-1 stay in registers.  Each plane is staged once per column
+// (plus the xy halo), where a box stages (T_z + 5) planes per T_z.
+// Two barriers per step keep the rings safe: the q store of step z goes to
+// the slot of plane z-2, whose last reader is step z-1's differences (before
+// that step's second barrier); the differences of step z go to the slot of
+// plane z-1, whose last reader is step z-1's faces (before step z's first
+// barrier).
+// The kernel stores the face values only; k_face_reduce forms their velocity
+// sums.
+template <typename ST, bool DIR, bool SS, int TX, int TY>
+struct ZMarch {
+    using CT = typename StoreT<ST>::C;
+    using RT = typename StoreT<ST>::R;
+    static constexpr int NT = TX * TY;
+    static constexpr int QX = TX + 5, QY = TY + 5, NQ = QX * QY;  // q plane
+    static constexpr int AX = TX + 3, AY = TY + 3, NA = AX * AY;  // difference plane
+    static constexpr int NSLOT = (NQ + NT - 1) / NT;              // q points per thread
+    static constexpr int NPASS = (2 * NA + NT - 1) / NT;          // (point, field) passes
+    struct Smem {
+        CT q[4][2][NQ];
+        CT a[2][2][3][NA];  // [ring][field][component][point]
+    };
+    __device__ static int qidx(int x, int y) { return (x + 3) + QX * (y + 3); }
+    __device__ static int aidx(int x, int y) { return (x + 2) + AX * (y + 2); }
+
+    __device__ static void run(const Problem& P, int tile, int i, Smem& sm) {
+        const int tid = threadIdx.x;
+        const int ox = (tile % P.tiles1[0]) * TX, oy = (tile / P.tiles1[0]) * TY;
+        const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
+        const long long nplane = (long long)n0 * n1;
+        // q-plane points of this thread: in-plane source offset after the
+        // periodic wrap / outflow clamp, and for Dirichlet sides the side of
+        // the point's x or y coordinate (2 d + side + 1, y over x, 0: none)
+        long long off[NSLOT];
+        int lq[NSLOT];
+        int sxy[DIR ? NSLOT : 1];
+#pragma unroll
+        for (int k = 0; k < NSLOT; ++k) {
+            const int p = tid + k * NT;
+            lq[k] = p < NQ ? p : -1;
+            const int pp = p < NQ ? p : 0;
+            const int x = ox + pp % QX - 3, y = oy + pp / QX - 3;
+            off[k] = map_coord(x, n0, P.bc[0]) + (long long)n0 * map_coord(y, n1, P.bc[1]);
+            if constexpr (DIR) {
+                int side = 0;
+                if (P.bc[0] == 2 && (x < 0 || x >= n0)) side = (x >= n0) + 1;
+                if (P.bc[1] == 2 && (y < 0 || y >= n1)) side = 2 + (y >= n1) + 1;
+                sxy[k] = side;
+            }
+        }
+        const Vel v = load_vel(P.vel, i);
+        const unsigned shift = StoreT<ST>::MIXED ? (unsigned)(row_word(P, i) & 1) << 4 : 0u;
+
+        RT pg[NSLOT], pb[NSLOT];  // raw fields of the next plane to stage
+        auto load_plane = [&](int z) __attribute__((always_inline)) {
+            const long long base = (long long)map_coord(z, n2, P.bc[2]) * nplane;
+            long long src[NSLOT];
+#pragma unroll
+            for (int k = 0; k < NSLOT; ++k) src[k] = base + off[k];
+            load_slots<ST, NSLOT>(P, P.qg, P.qb, i, src, pg, pb);
+        };
+        auto store_plane = [&](int z) __attribute__((always_inline)) {
+            const int r = (z + 8) & 3;
+            int zs = 0;  // Dirichlet side of the plane (z over x and y)
+            if constexpr (DIR) {
+                if (P.bc[2] == 2 && (z < 0 || z >= n2)) zs = 4 + (z >= n2) + 1;
+            }
+#pragma unroll
+            for (int k = 0; k < NSLOT; ++k) {
+                if (lq[k] < 0) continue;
+                double g = slot_value<ST>(pg[k], shift), b = slot_value<ST>(pb[k], shift);
+                if constexpr (DIR) {
+                    const int side = zs ? zs : sxy[k];
+                    if (side) {
+                        const double* de = P.dir_eq + ((long long)(side - 1) * P.V + i) * 2;
+                        g = de[0];
+                        b = de[1];
+                    }
+                }
+                sm.q[r][0][lq[k]] = CT(g);
+                sm.q[r][1][lq[k]] = CT(b);
+            }
+        };
+        // limited differences of plane z on the difference plane
+        auto differences = [&](int z) __attribute__((always_inline)) {
+            const int rm = (z + 7) & 3, r0 = (z + 8) & 3, rp = (z + 9) & 3, ra = (z + 8) & 1;
+#pragma unroll
+            for (int k = 0; k < NPASS; ++k) {
+                const int t = tid + k * NT;
+                if (t < 2 * NA) {
+                    const int f = t >= NA;
+                    const int pt = t - f * NA;
+                    const int qi = (pt % AX + 1) + QX * (pt / AX + 1);
+                    const CT* q = sm.q[r0][f];
+                    const CT c = q[qi];
+                    sm.a[ra][f][0][pt] = half_van_leer(c - q[qi - 1], q[qi + 1] - c);
+                    sm.a[ra][f][1][pt] = half_van_leer(c - q[qi - QX], q[qi + QX] - c);
+                    sm.a[ra][f][2][pt] = half_van_leer(c - sm.q[rm][f][qi], sm.q[rp][f][qi] - c);
+                }
+            }
+        };
+
+        // own cell, the validity of its left faces and their face-grid index
+        const int tx = tid % TX, ty = tid / TX;
+        const int gx = ox + tx, gy = oy + ty;
+        const bool vx = gx < P.ne[0] && gy < n1, vy = gx < n0 && gy < P.ne[1], vz = gx < n0 && gy < n1;
+        const long long fplane = (long long)P.ne[0] * P.ne[1];
+        const long long fe0 = gx + (long long)P.ne[0] * gy;
+        const long long fstride = P.fv_stride;
+        const int qo_i = qidx(tx, ty), ao_i = aidx(tx, ty);
+
+        CT am2[2][3], am1[2][3], qm1[2];  // own column: differences of z-2, z-1; q of z-1
+        auto faces = [&](int z, bool emit) __attribute__((always_inline)) {
+            const int rq = (z + 8) & 3, ra = (z + 8) & 1, ra1 = (z + 9) & 1;
+            CT qo[2], ao[2][3];
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                qo[f] = sm.q[rq][f][qo_i];
+#pragma unroll
+                for (int e = 0; e < 3; ++e) ao[f][e] = sm.a[ra][f][e][ao_i];
+            }
+            if (emit) {
+                const long long fe = fe0 + fplane * z;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const bool valid = d == 0 ? (vx && z < n2) : (d == 1 ? (vy && z < n2) : vz);
+                    const int dx = d == 0, dy = d == 1;
+                    const int a_m = aidx(tx - dx, ty - dy), a_mm = aidx(tx - 2 * dx, ty - 2 * dy);
+                    const int a_p = aidx(tx + dx, ty + dy), q_m = qidx(tx - dx, ty - dy);
+                    // the face value from the upwind cell c - d (left) or c (right)
+                    auto left_value = [&](int f) __attribute__((always_inline)) {
+                        CT qU, aU[3], aL[3];
+                        if (d == 2) {
+                            qU = qm1[f];
+#pragma unroll
+                            for (int e = 0; e < 3; ++e) {
+                                aU[e] = am1[f][e];
+                                aL[e] = am2[f][e];
+                            }
+                        } else {
+                            qU = sm.q[rq][f][q_m];
+#pragma unroll
+                            for (int e = 0; e < 3; ++e) {
+                                aU[e] = sm.a[ra][f][e][a_m];
+                                aL[e] = sm.a[ra][f][e][a_mm];
+                            }
+                        }
+                        if constexpr (SS) return face_value_single<3, CT>(qU, aU, d, CT(1), v);
+                        return face_value_at<3, CT>(qU, aU, aL, ao[f], d, CT(1), v);
+                    };
+                    auto right_value = [&](int f) __attribute__((always_inline)) {
+                        if constexpr (SS) return face_value_single<3, CT>(qo[f], ao[f], d, CT(-1), v);
+                        CT aL[3], aR[3];
+#pragma unroll
+                        for (int e = 0; e < 3; ++e) {
+                            aL[e] = d == 2 ? am1[f][e] : sm.a[ra][f][e][a_m];
+                            aR[e] = d == 2 ? sm.a[ra1][f][e][ao_i] : sm.a[ra][f][e][a_p];
+                        }
+                        return face_value_at<3, CT>(qo[f], ao[f], aL, aR, d, CT(-1), v);
+                    };
+                    // upwind side by the bits of the uniform xi_d, as in the
+                    // box kernel
+                    const long long xbits = __builtin_bit_cast(long long, v.xi[d]);
+                    const bool from_left = xbits > 0;
+                    const bool from_right = xbits < 0 && (xbits << 1) != 0;
+                    CT fv[2];
+                    if (from_left) {
+                        fv[0] = left_value(0);
+                        fv[1] = left_value(1);
+                    } else if (from_right) {
+                        fv[0] = right_value(0);
+                        fv[1] = right_value(1);
+                    } else {
+                        fv[0] = CT(0.5) * (left_value(0) + right_value(0));
+                        fv[1] = CT(0.5) * (left_value(1) + right_value(1));
+                    }
+                    if (valid) {
+                        const long long o = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch + fe;
+                        st_stream<CT>(P.FV, o, fv[0]);
+                        st_stream<CT>(P.FV, o + fstride, fv[1]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                qm1[f] = qo[f];
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    am2[f][e] = am1[f][e];
+                    am1[f][e] = ao[f][e];
+                }
+            }
+        };
+
+        // Planes z0-3 and z0-2 first; then step z stages plane z+2 (loaded
+        // during the previous step), loads plane z+3, forms the differences of
+        // plane z+1 and, from z0 on, the faces of plane z.  The steps before
+        // z0 only fill the rings and the column registers (the differences of
+        // plane z0-3 they shift through are never used).  The last step's
+        // load of a plane past the column reads a mapped, valid address.
+        const int z0 = 0, z1 = P.ne[2];
+        load_plane(z0 - 3);
+        store_plane(z0 - 3);
+        load_plane(z0 - 2);
+        store_plane(z0 - 2);
+        load_plane(z0 - 1);
+        for (int z = z0 - 3; z < z1; ++z) {
+            store_plane(z + 2);
+            load_plane(z + 3);
+            __syncthreads();
+            differences(z + 1);
+            __syncthreads();
+            faces(z, z >= z0);
+        }
+    }
+};
+
+template <typename ST, bool DIR, bool SS, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_face_values_z(Problem P) {
+    using K = ZMarch<ST, DIR, SS, TX, TY>;
+    __shared__ typename K::Smem sm;
+    const int ntiles = P.tiles1[0] * P.tiles1[1];
+    const int q = xcd_remap(blockIdx.x, gridDim.x);
+    K::run(P, q % ntiles, q / ntiles, sm);
+}
+
+// Velocity sums of the stored face values of one velocity slice: per face
+// along d, the 2D+3 sums of the box kernel with the same products in the same
+// ascending-velocity order, so the partial sums are bitwise those the box
+// kernel accumulates in registers.  One thread per face-grid point takes its
+// D faces.
+template <int D, typename CT>
+__global__ __launch_bounds__(WG) void k_face_reduce(Problem P) {
+    const long long fe = (long long)blockIdx.x * WG + threadIdx.x;
+    const int slice = blockIdx.y;
+    if (fe >= P.NE) return;
+    const int c[3] = {(int)(fe % P.ne[0]), (int)((fe / P.ne[0]) % P.ne[1]),
+                      (int)(fe / ((long long)P.ne[0] * P.ne[1]))};
+    bool valid[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        bool ok = true;
+#pragma unroll
+        for (int e = 0; e < D; ++e) ok &= e == d ? c[e] < P.ne[e] : c[e] < P.n[e];
+        valid[d] = ok;
+    }
+    const int v0 = (int)((long long)P.V * slice / P.nslices);
+    const int v1 = (int)((long long)P.V * (slice + 1) / P.nslices);
+    constexpr int NS = 2 * D + 3;
+    double acc[D][NS];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int j = 0; j < NS; ++j) acc[d][j] = 0.0;
+    const CT* const fv = (const CT*)P.FV + fe;
+#pragma unroll 4
+    for (int i = v0; i < v1; ++i) {
+        const Vel v = load_vel(P.vel, i);
+        const const_dptr vp = vel_ptr(P.vel, i);
+        const long long row = (long long)i * P.fv_pitch;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            // invalid faces read a stored slot of the block and discard it
+            const double vg = fv[(long long)(2 * d) * P.fv_stride + row];
+            const double vb2 = fv[(long long)(2 * d + 1) * P.fv_stride + row];
+            acc[d][0] += v.w * vg;
+#pragma unroll
+            for (int e = 0; e < D; ++e) acc[d][1 + e] += vp[VE_WXI0 + e] * vg;
+            acc[d][D + 1] += v.w * vb2;
+#pragma unroll
+            for (int e = 0; e < D; ++e) acc[d][D + 2 + e] += vp[VE_WXX + 3 * d + e] * vg;
+            acc[d][2 * D + 2] += vp[VE_WXI0 + d] * vb2;
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        if (!valid[d]) continue;
+        double* out = P.FS + ((long long)(slice * D + d) * NS) * P.NE + fe;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) out[(long long)j * P.NE] = acc[d][j];
+    }
+}
+
+// Face values by z-march, then their velocity sums (tile shape TID with z = 0).
+template <typename ST, bool DIR, bool SS, int TID>
+hipError_t launch_face_sums_zmarch(const Problem& P, hipStream_t s) {
+    constexpr TileExt T = tile_shape(3, TID);
+    static_assert(tile_zmarch(3, TID), "not a z-marching shape");
+    using K = ZMarch<ST, DIR, SS, T.x, T.y>;
+    static_assert(sizeof(typename K::Smem) == face_sum_lds_bytes(3, TID, sizeof(typename K::CT)),
+                  "host and kernel LDS sizes differ");
+    if constexpr (face_tile_fits(3, TID, sizeof(typename K::CT))) {
+        const unsigned nb = (unsigned)((long long)P.tiles1[0] * P.tiles1[1] * P.V);
+        hipLaunchKernelGGL((k_face_values_z<ST, DIR, SS, T.x, T.y>), dim3(nb), dim3(T.x * T.y), 0, s, P);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_face_reduce<3, typename K::CT>), dim3((unsigned)((P.NE + WG - 1) / WG), P.nslices),
+                           dim3(WG), 0, s, P);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidConfiguration;
+    }
+}
+
+template <typename ST, int TID>
+int face_values_z_occupancy() {
+    constexpr TileExt T = tile_shape(3, TID);
+    if constexpr (face_tile_fits(3, TID, sizeof(typename StoreT<ST>::C))) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_values_z<ST, false, false, T.x, T.y>),
+                                                        T.x * T.y, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        return n;
+    } else {
+        return 0;
+    }
+}
+
 // Batched face sums: one launch for every tile of every problem of a storage
 // class.  Persistent: the grid covers the resident slots and the workgroups
 // take (cost-sorted, largest first) items from a device queue: an atomic

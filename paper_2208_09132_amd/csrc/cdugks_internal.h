@@ -144,18 +144,24 @@ hipError_t launch_cell_close_batched(const Problem* probs, const long long* offs
 int tile_blocks_per_cu(int D, int storage, bool update);
 
 // Face-sum tile shapes: cells per workgroup along x, y, z, one thread per
-// cell.  Shape 0 of each dimension is the default; the autotuner (or the
-// caller, cdugks_params.face_tile) may choose another for a problem.  A
-// cell's arithmetic does not depend on the tile it sits in (in 2-D every
-// shape keeps its q-box slots in registers, see Geo), and the velocity split
-// is planned with the default shape, so every shape gives bitwise the same
-// result.  Shapes wider along x use more of each 128-byte line of a halo row;
-// shapes of 768 cells stage larger boxes per workgroup (less halo per cell).
+// cell.  Shape 0 of each dimension plans the velocity split and is the shape
+// of batched launches; default_face_tile(D) is the one a single problem runs
+// unless the caller (cdugks_params.face_tile) or the autotuner chooses
+// another.  A cell's arithmetic does not depend on the tile it sits in (in
+// 2-D every shape keeps its q-box slots in registers, see Geo), and the
+// velocity split is planned with shape 0, so every shape gives bitwise the
+// same result.  Shapes wider along x use more of each 128-byte line of a halo
+// row; shapes of 768 cells stage larger boxes per workgroup (less halo per
+// cell).
+// 3-D shapes with z = 0 are z-marching columns: a workgroup of x * y threads
+// owns an x * y column of the face grid for one velocity and walks it along
+// z (ZMarch in cdugks_device.h), so each staged plane serves the three planes
+// of faces that need it instead of being staged again by the tile above.
 struct TileExt {
     int x, y, z;
 };
-constexpr int MAX_TILE_SHAPES = 6;
-constexpr int tile_shape_count(int D) { return D == 1 ? 1 : (D == 2 ? 4 : 6); }
+constexpr int MAX_TILE_SHAPES = 9;
+constexpr int tile_shape_count(int D) { return D == 1 ? 1 : (D == 2 ? 4 : 9); }
 constexpr TileExt tile_shape(int D, int id) {
     if (D == 1) return TileExt{256, 1, 1};
     if (D == 2) {
@@ -172,20 +178,27 @@ constexpr TileExt tile_shape(int D, int id) {
     case 3: return TileExt{32, 6, 4};
     case 4: return TileExt{64, 4, 3};
     case 5: return TileExt{16, 8, 6};
+    case 6: return TileExt{16, 16, 0};
+    case 7: return TileExt{32, 8, 0};
+    case 8: return TileExt{32, 16, 0};
     default: return TileExt{16, 4, 4};
     }
 }
+constexpr bool tile_zmarch(int D, int id) { return D == 3 && tile_shape(D, id).z == 0; }
+constexpr int default_face_tile(int D) { return D == 3 ? 6 : 0; }
 constexpr int tile_threads(int D, int id) {
-    return tile_shape(D, id).x * tile_shape(D, id).y * tile_shape(D, id).z;
+    return tile_shape(D, id).x * tile_shape(D, id).y * (tile_zmarch(D, id) ? 1 : tile_shape(D, id).z);
 }
 // Static LDS of a face-sum workgroup (element size es of the stencil
-// arithmetic): q box and limited-difference box for g and b, double-buffered
-// in 1-D and 2-D.  Shapes whose boxes exceed the 160 KB of a CU do not exist
-// for that storage form.
+// arithmetic).  Box shapes: q box and limited-difference box for g and b,
+// double-buffered in 1-D and 2-D.  z-marching columns: a ring of four q
+// planes and a ring of two planes of the three limited differences.  Shapes
+// whose LDS exceeds the 160 KB of a CU do not exist for that storage form.
 constexpr long long face_sum_lds_bytes(int D, int id, int es) {
     const TileExt t = tile_shape(D, id);
     const long long qx = t.x + 5, qy = D >= 2 ? t.y + 5 : 1, qz = D >= 3 ? t.z + 5 : 1;
     const long long ax = t.x + 3, ay = D >= 2 ? t.y + 3 : 1, az = D >= 3 ? t.z + 3 : 1;
+    if (tile_zmarch(D, id)) return 2LL * es * (4 * qx * qy + 2 * 3 * ax * ay);
     const long long nbuf = D <= 2 ? 2 : 1;
     return nbuf * 2 * es * (qx * qy * qz + D * ax * ay * az);
 }

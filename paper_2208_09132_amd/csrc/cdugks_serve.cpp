@@ -68,7 +68,7 @@ int device_cus() {
 struct TuneEntry {
     int upd_slices = 0;   // 0 = the occupancy rule
     int grid_factor = 1;  // persistent grid = factor x resident slots
-    int face_tile = 0;    // face-sum tile shape of single-problem launches (0 = default)
+    int face_tile = -1;   // face-sum tile shape of single-problem launches (-1: the default)
 };
 
 std::mutex g_tune_mu;
@@ -94,9 +94,9 @@ void tune_load_locked() {
     char line[256];
     while (fgets(line, sizeof line, f)) {
         char key[128];
-        int us = 0, gf = 1, ft = 0;
+        int us = 0, gf = 1, ft = -1;
         const int got = sscanf(line, "%127s %d %d %d", key, &us, &gf, &ft);
-        if (got >= 3) g_tune[key] = TuneEntry{us, gf, got == 4 ? ft : 0};
+        if (got >= 3) g_tune[key] = TuneEntry{us, gf, got == 4 ? ft : -1};
     }
     fclose(f);
 }
