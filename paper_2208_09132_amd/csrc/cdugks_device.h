@@ -1216,17 +1216,26 @@ int face_sum_occupancy_shape() {
 // that step's second barrier); the differences of step z go to the slot of
 // plane z-1, whose last reader is step z-1's faces (before step z's first
 // barrier).
+// NF threads per cell: with NF = 2 (FP64, whose LDS allows two workgroups per
+// CU) one thread per cell takes g and another b, which doubles the waves that
+// hide the LDS and memory latency; with NF = 1 a thread takes both fields.
 // The kernel stores the face values only; k_face_reduce forms their velocity
 // sums.
+template <typename CT>
+constexpr int zmarch_threads_per_cell() { return sizeof(CT) == 8 ? 2 : 1; }
+
 template <typename ST, bool DIR, bool SS, int TX, int TY>
 struct ZMarch {
     using CT = typename StoreT<ST>::C;
     using RT = typename StoreT<ST>::R;
-    static constexpr int NT = TX * TY;
+    static constexpr int NT = TX * TY;                        // cells of the column
+    static constexpr int NF = zmarch_threads_per_cell<CT>();  // threads per cell
+    static constexpr int NTH = NF * NT;                       // threads of the workgroup
+    static constexpr int FL = 2 / NF;                         // fields per thread
     static constexpr int QX = TX + 5, QY = TY + 5, NQ = QX * QY;  // q plane
     static constexpr int AX = TX + 3, AY = TY + 3, NA = AX * AY;  // difference plane
     static constexpr int NSLOT = (NQ + NT - 1) / NT;              // q points per thread
-    static constexpr int NPASS = (2 * NA + NT - 1) / NT;          // (point, field) passes
+    static constexpr int NPASS = (2 * NA + NTH - 1) / NTH;        // (point, field) passes
     struct Smem {
         CT q[4][2][NQ];
         CT a[2][2][3][NA];  // [ring][field][component][point]
@@ -1236,6 +1245,8 @@ struct ZMarch {
 
     __device__ static void run(const Problem& P, int tile, int i, Smem& sm) {
         const int tid = threadIdx.x;
+        const int ct = tid % NT;           // cell of the column
+        const int f0 = NF == 2 ? tid / NT : 0;  // first field of the thread (uniform per wave)
         const int ox = (tile % P.tiles1[0]) * TX, oy = (tile / P.tiles1[0]) * TY;
         const int n0 = P.n[0], n1 = P.n[1], n2 = P.n[2];
         const long long nplane = (long long)n0 * n1;
@@ -1247,7 +1258,7 @@ struct ZMarch {
         int sxy[DIR ? NSLOT : 1];
 #pragma unroll
         for (int k = 0; k < NSLOT; ++k) {
-            const int p = tid + k * NT;
+            const int p = ct + k * NT;
             lq[k] = p < NQ ? p : -1;
             const int pp = p < NQ ? p : 0;
             const int x = ox + pp % QX - 3, y = oy + pp / QX - 3;
@@ -1262,13 +1273,20 @@ struct ZMarch {
         const Vel v = load_vel(P.vel, i);
         const unsigned shift = StoreT<ST>::MIXED ? (unsigned)(row_word(P, i) & 1) << 4 : 0u;
 
-        RT pg[NSLOT], pb[NSLOT];  // raw fields of the next plane to stage
+        // raw fields of the next plane to stage: both, or the thread's one
+        RT pg[NSLOT], pb[NSLOT];
         auto load_plane = [&](int z) __attribute__((always_inline)) {
             const long long base = (long long)map_coord(z, n2, P.bc[2]) * nplane;
             long long src[NSLOT];
 #pragma unroll
             for (int k = 0; k < NSLOT; ++k) src[k] = base + off[k];
-            load_slots<ST, NSLOT>(P, P.qg, P.qb, i, src, pg, pb);
+            if constexpr (NF == 1) {
+                load_slots<ST, NSLOT>(P, P.qg, P.qb, i, src, pg, pb);
+            } else {
+                const void* const q = f0 ? P.qb : P.qg;
+#pragma unroll
+                for (int k = 0; k < NSLOT; ++k) pg[k] = state_load<ST>(P, q, i, src[k]);
+            }
         };
         auto store_plane = [&](int z) __attribute__((always_inline)) {
             const int r = (z + 8) & 3;
@@ -1279,17 +1297,16 @@ struct ZMarch {
 #pragma unroll
             for (int k = 0; k < NSLOT; ++k) {
                 if (lq[k] < 0) continue;
-                double g = slot_value<ST>(pg[k], shift), b = slot_value<ST>(pb[k], shift);
-                if constexpr (DIR) {
-                    const int side = zs ? zs : sxy[k];
-                    if (side) {
-                        const double* de = P.dir_eq + ((long long)(side - 1) * P.V + i) * 2;
-                        g = de[0];
-                        b = de[1];
+#pragma unroll
+                for (int j = 0; j < FL; ++j) {
+                    const int f = f0 + j;
+                    double val = slot_value<ST>(j == 0 ? pg[k] : pb[k], shift);
+                    if constexpr (DIR) {
+                        const int side = zs ? zs : sxy[k];
+                        if (side) val = P.dir_eq[((long long)(side - 1) * P.V + i) * 2 + f];
                     }
+                    sm.q[r][f][lq[k]] = CT(val);
                 }
-                sm.q[r][0][lq[k]] = CT(g);
-                sm.q[r][1][lq[k]] = CT(b);
             }
         };
         // limited differences of plane z on the difference plane
@@ -1297,7 +1314,7 @@ struct ZMarch {
             const int rm = (z + 7) & 3, r0 = (z + 8) & 3, rp = (z + 9) & 3, ra = (z + 8) & 1;
 #pragma unroll
             for (int k = 0; k < NPASS; ++k) {
-                const int t = tid + k * NT;
+                const int t = tid + k * NTH;
                 if (t < 2 * NA) {
                     const int f = t >= NA;
                     const int pt = t - f * NA;
@@ -1312,7 +1329,7 @@ struct ZMarch {
         };
 
         // own cell, the validity of its left faces and their face-grid index
-        const int tx = tid % TX, ty = tid / TX;
+        const int tx = ct % TX, ty = ct / TX;
         const int gx = ox + tx, gy = oy + ty;
         const bool vx = gx < P.ne[0] && gy < n1, vy = gx < n0 && gy < P.ne[1], vz = gx < n0 && gy < n1;
         const long long fplane = (long long)P.ne[0] * P.ne[1];
@@ -1320,15 +1337,17 @@ struct ZMarch {
         const long long fstride = P.fv_stride;
         const int qo_i = qidx(tx, ty), ao_i = aidx(tx, ty);
 
-        CT am2[2][3], am1[2][3], qm1[2];  // own column: differences of z-2, z-1; q of z-1
+        // own column, per field of the thread: differences of planes z-2 and
+        // z-1, q of plane z-1
+        CT am2[FL][3], am1[FL][3], qm1[FL];
         auto faces = [&](int z, bool emit) __attribute__((always_inline)) {
             const int rq = (z + 8) & 3, ra = (z + 8) & 1, ra1 = (z + 9) & 1;
-            CT qo[2], ao[2][3];
+            CT qo[FL], ao[FL][3];
 #pragma unroll
-            for (int f = 0; f < 2; ++f) {
-                qo[f] = sm.q[rq][f][qo_i];
+            for (int j = 0; j < FL; ++j) {
+                qo[j] = sm.q[rq][f0 + j][qo_i];
 #pragma unroll
-                for (int e = 0; e < 3; ++e) ao[f][e] = sm.a[ra][f][e][ao_i];
+                for (int e = 0; e < 3; ++e) ao[j][e] = sm.a[ra][f0 + j][e][ao_i];
             }
             if (emit) {
                 const long long fe = fe0 + fplane * z;
@@ -1338,15 +1357,17 @@ struct ZMarch {
                     const int dx = d == 0, dy = d == 1;
                     const int a_m = aidx(tx - dx, ty - dy), a_mm = aidx(tx - 2 * dx, ty - 2 * dy);
                     const int a_p = aidx(tx + dx, ty + dy), q_m = qidx(tx - dx, ty - dy);
-                    // the face value from the upwind cell c - d (left) or c (right)
-                    auto left_value = [&](int f) __attribute__((always_inline)) {
+                    // the face value from the upwind cell c - d (left) or c
+                    // (right), for field slot j of the thread
+                    auto left_value = [&](int j) __attribute__((always_inline)) {
+                        const int f = f0 + j;
                         CT qU, aU[3], aL[3];
                         if (d == 2) {
-                            qU = qm1[f];
+                            qU = qm1[j];
 #pragma unroll
                             for (int e = 0; e < 3; ++e) {
-                                aU[e] = am1[f][e];
-                                aL[e] = am2[f][e];
+                                aU[e] = am1[j][e];
+                                aL[e] = am2[j][e];
                             }
                         } else {
                             qU = sm.q[rq][f][q_m];
@@ -1357,48 +1378,49 @@ struct ZMarch {
                             }
                         }
                         if constexpr (SS) return face_value_single<3, CT>(qU, aU, d, CT(1), v);
-                        return face_value_at<3, CT>(qU, aU, aL, ao[f], d, CT(1), v);
+                        return face_value_at<3, CT>(qU, aU, aL, ao[j], d, CT(1), v);
                     };
-                    auto right_value = [&](int f) __attribute__((always_inline)) {
-                        if constexpr (SS) return face_value_single<3, CT>(qo[f], ao[f], d, CT(-1), v);
+                    auto right_value = [&](int j) __attribute__((always_inline)) {
+                        const int f = f0 + j;
+                        if constexpr (SS) return face_value_single<3, CT>(qo[j], ao[j], d, CT(-1), v);
                         CT aL[3], aR[3];
 #pragma unroll
                         for (int e = 0; e < 3; ++e) {
-                            aL[e] = d == 2 ? am1[f][e] : sm.a[ra][f][e][a_m];
+                            aL[e] = d == 2 ? am1[j][e] : sm.a[ra][f][e][a_m];
                             aR[e] = d == 2 ? sm.a[ra1][f][e][ao_i] : sm.a[ra][f][e][a_p];
                         }
-                        return face_value_at<3, CT>(qo[f], ao[f], aL, aR, d, CT(-1), v);
+                        return face_value_at<3, CT>(qo[j], ao[j], aL, aR, d, CT(-1), v);
                     };
                     // upwind side by the bits of the uniform xi_d, as in the
                     // box kernel
                     const long long xbits = __builtin_bit_cast(long long, v.xi[d]);
                     const bool from_left = xbits > 0;
                     const bool from_right = xbits < 0 && (xbits << 1) != 0;
-                    CT fv[2];
+                    CT fv[FL];
                     if (from_left) {
-                        fv[0] = left_value(0);
-                        fv[1] = left_value(1);
+#pragma unroll
+                        for (int j = 0; j < FL; ++j) fv[j] = left_value(j);
                     } else if (from_right) {
-                        fv[0] = right_value(0);
-                        fv[1] = right_value(1);
+#pragma unroll
+                        for (int j = 0; j < FL; ++j) fv[j] = right_value(j);
                     } else {
-                        fv[0] = CT(0.5) * (left_value(0) + right_value(0));
-                        fv[1] = CT(0.5) * (left_value(1) + right_value(1));
+#pragma unroll
+                        for (int j = 0; j < FL; ++j) fv[j] = CT(0.5) * (left_value(j) + right_value(j));
                     }
                     if (valid) {
-                        const long long o = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch + fe;
-                        st_stream<CT>(P.FV, o, fv[0]);
-                        st_stream<CT>(P.FV, o + fstride, fv[1]);
+                        const long long o = (long long)(2 * d + f0) * fstride + (long long)i * P.fv_pitch + fe;
+#pragma unroll
+                        for (int j = 0; j < FL; ++j) st_stream<CT>(P.FV, o + j * fstride, fv[j]);
                     }
                 }
             }
 #pragma unroll
-            for (int f = 0; f < 2; ++f) {
-                qm1[f] = qo[f];
+            for (int j = 0; j < FL; ++j) {
+                qm1[j] = qo[j];
 #pragma unroll
                 for (int e = 0; e < 3; ++e) {
-                    am2[f][e] = am1[f][e];
-                    am1[f][e] = ao[f][e];
+                    am2[j][e] = am1[j][e];
+                    am1[j][e] = ao[j][e];
                 }
             }
         };
@@ -1427,7 +1449,7 @@ struct ZMarch {
 };
 
 template <typename ST, bool DIR, bool SS, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void k_face_values_z(Problem P) {
+__global__ __launch_bounds__((ZMarch<ST, DIR, SS, TX, TY>::NTH)) void k_face_values_z(Problem P) {
     using K = ZMarch<ST, DIR, SS, TX, TY>;
     __shared__ typename K::Smem sm;
     const int ntiles = P.tiles1[0] * P.tiles1[1];
@@ -1502,7 +1524,7 @@ hipError_t launch_face_sums_zmarch(const Problem& P, hipStream_t s) {
                   "host and kernel LDS sizes differ");
     if constexpr (face_tile_fits(3, TID, sizeof(typename K::CT))) {
         const unsigned nb = (unsigned)((long long)P.tiles1[0] * P.tiles1[1] * P.V);
-        hipLaunchKernelGGL((k_face_values_z<ST, DIR, SS, T.x, T.y>), dim3(nb), dim3(T.x * T.y), 0, s, P);
+        hipLaunchKernelGGL((k_face_values_z<ST, DIR, SS, T.x, T.y>), dim3(nb), dim3(K::NTH), 0, s, P);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_face_reduce<3, typename K::CT>), dim3((unsigned)((P.NE + WG - 1) / WG), P.nslices),
@@ -1519,7 +1541,7 @@ int face_values_z_occupancy() {
     if constexpr (face_tile_fits(3, TID, sizeof(typename StoreT<ST>::C))) {
         int n = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_face_values_z<ST, false, false, T.x, T.y>),
-                                                        T.x * T.y, 0) != hipSuccess) {
+                                                        ZMarch<ST, false, false, T.x, T.y>::NTH, 0) != hipSuccess) {
             (void)hipGetLastError();
             return 0;
         }
