@@ -4,7 +4,7 @@ Three kinds of summary, all markdown with a machine-readable JSON block:
 
 * ``trace``: the ``*_kernel_stats.csv`` of a ``--kernel-trace --stats`` run,
   one row per kernel (calls, average, min, max duration).
-* ``pmc``: HBM traffic of one kernel from two ``--pmc`` runs, ``FETCH_SIZE``
+* ``pmc``: HBM traffic of one kernel (or the kernels of one phase) from two ``--pmc`` runs, ``FETCH_SIZE``
   then ``WRITE_SIZE`` (KiB per dispatch).  Each counter is scaled by what it
   reads for a plain copy kernel of known size in the same run: the library's
   FP64-to-FP64 distribution copy (``k_to_f64<double>``, n doubles read and n
@@ -117,17 +117,24 @@ def write_trace(csv_dir, out, title, command, note="", tail_kernels=(), tail=10)
         f.write("\n".join(lines))
 
 
-def write_pmc(fetch_dir, write_dir, out, kernel, title, commands, units_per_launch, algo_bytes_per_unit,
+def write_pmc(fetch_dir, write_dir, out, kernels, title, commands, units_per_launch, algo_bytes_per_unit,
               copy_bytes):
+    """HBM traffic of one launch of a phase: the kernels it runs (one
+    dispatch each per phase), each counter scaled by the copy kernel's."""
     fm, wm = counter_means(fetch_dir, "FETCH_SIZE"), counter_means(write_dir, "WRITE_SIZE")
-    k_f, k_w = _find(fm, kernel), _find(wm, kernel)
     c_f, c_w = _find(fm, COPY_PATTERN), _find(wm, COPY_PATTERN)
     f_fac = copy_bytes / (fm[c_f] * 1024.0)
     w_fac = copy_bytes / (wm[c_w] * 1024.0)
-    fetch = fm[k_f] * 1024.0 * f_fac
-    write = wm[k_w] * 1024.0 * w_fac
+    per = []
+    for pat in kernels:
+        k_f, k_w = _find(fm, pat), _find(wm, pat)
+        per.append({"kernel": k_f, "fetch_kib_raw": fm[k_f], "write_kib_raw": wm[k_w],
+                    "fetch_bytes": fm[k_f] * 1024.0 * f_fac, "write_bytes": wm[k_w] * 1024.0 * w_fac})
+    fetch = sum(k["fetch_bytes"] for k in per)
+    write = sum(k["write_bytes"] for k in per)
     algo = units_per_launch * algo_bytes_per_unit
-    rec = {"digest": source_digest(), "kernel": k_f, "fetch_kib_raw": fm[k_f], "write_kib_raw": wm[k_w],
+    rec = {"digest": source_digest(), "kernel": per[0]["kernel"], "kernels": per,
+           "fetch_kib_raw": sum(k["fetch_kib_raw"] for k in per), "write_kib_raw": sum(k["write_kib_raw"] for k in per),
            "copy_kernel": c_f, "copy_bytes": copy_bytes, "copy_fetch_kib_raw": fm[c_f],
            "copy_write_kib_raw": wm[c_w],
            "fetch_factor": f_fac, "write_factor": w_fac, "fetch_bytes": fetch, "write_bytes": write,
@@ -140,10 +147,17 @@ def write_pmc(fetch_dir, write_dir, out, kernel, title, commands, units_per_laun
               f"dispatch; its FETCH_SIZE reads {fm[c_f]:.0f} KiB (factor {f_fac:.3f}) and its WRITE_SIZE "
               f"{wm[c_w]:.0f} KiB (factor {w_fac:.3f}).", "",
               "| kernel | FETCH_SIZE (KiB) | WRITE_SIZE (KiB) | fetch (GB) | write (GB) | total (GB) | "
-              "algorithmic (GB) |", "|---|---|---|---|---|---|---|",
-              f"| `{k_f[:80]}` | {fm[k_f]:.0f} | {wm[k_w]:.0f} | {fetch / 1e9:.3f} | {write / 1e9:.3f} | "
-              f"{(fetch + write) / 1e9:.3f} | {algo / 1e9:.3f} |", "",
-              "```json", json.dumps(rec, indent=1), "```", ""]
+              "algorithmic (GB) |", "|---|---|---|---|---|---|---|"]
+    for k in per:
+        lines.append(f"| `{k['kernel'][:80]}` | {k['fetch_kib_raw']:.0f} | {k['write_kib_raw']:.0f} | "
+                     f"{k['fetch_bytes'] / 1e9:.3f} | {k['write_bytes'] / 1e9:.3f} | "
+                     f"{(k['fetch_bytes'] + k['write_bytes']) / 1e9:.3f} | |")
+    if len(per) > 1:
+        lines.append(f"| phase total | | | {fetch / 1e9:.3f} | {write / 1e9:.3f} | {(fetch + write) / 1e9:.3f} | "
+                     f"{algo / 1e9:.3f} |")
+    else:
+        lines[-1] = lines[-1][:-2] + f"{algo / 1e9:.3f} |"
+    lines += ["", "```json", json.dumps(rec, indent=1), "```", ""]
     with open(out, "w") as f:
         f.write("\n".join(lines))
 
@@ -199,7 +213,8 @@ def main():
     p.add_argument("fetch_dir")
     p.add_argument("write_dir")
     p.add_argument("out")
-    p.add_argument("--kernel", required=True, help="regex selecting one kernel name")
+    p.add_argument("--kernel", action="append", required=True,
+                   help="regex selecting one kernel name; repeat for a phase of several kernels")
     p.add_argument("--title", required=True)
     p.add_argument("--command", action="append", required=True)
     p.add_argument("--units", type=float, required=True, help="updates per launch")
