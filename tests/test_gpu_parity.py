@@ -179,6 +179,33 @@ def test_3d_full_size_five_steps_at_a_cell():
         assert max(errs) <= tol, (storage, errs)
 
 
+def test_3d_full_size_two_steps_at_sixteen_sampled_cells():
+    """The 3-D workload at full size (64^3 x 16^3), 2 steps in the launch
+    configuration the benchmark times, FP64 and FP32, against the oracle at 16
+    seeded cells anywhere in the grid (periodic wraps included), each from the
+    oracle on the 13^3 block within the 2-step reach of the cell."""
+    p = wl.shear3d(storage="f64")
+    steps = 2
+    rng = wl.SplitMix64(3091)
+    cells = [[rng.integer(0, 63) for _ in range(3)] for _ in range(16)]
+    runs = {}
+    for storage in ("f64", "f32"):
+        _log(f"  GPU {storage}, 64^3 x 16^3, {steps} steps")
+        runs[storage] = gpu_run(dict(p, storage=storage), steps)
+    dt = dt_checked(p, runs["f64"][1])
+    worst = {"f64": 0.0, "f32": 0.0}
+    for centre in cells:
+        q, full_idx, local = patch_problem(p, centre, 3 * steps)
+        r = oracle_run(q, dt, steps)
+        ref = (r[0][local], r[1][:, local], r[2][local])
+        for storage, tol in (("f64", 1e-12), ("f32", 1e-5)):
+            got = runs[storage][0]
+            errs = moment_errors(ref, (got[0][full_idx], got[1][:, full_idx], got[2][full_idx]))
+            worst[storage] = max(worst[storage], max(errs))
+            assert max(errs) <= tol, (centre, storage, errs)
+    _log(f"3-D full size at 16 sampled cells: largest errors {worst}")
+
+
 @pytest.mark.parametrize("kn", [1e-1, 10.0])
 def test_3d_full_size_other_knudsen_numbers_at_a_cell(kn):
     """The 3-D workload's other Knudsen numbers at full size (FP32 storage,
