@@ -425,15 +425,22 @@ struct FaceCoef {
 #pragma unroll
         for (int e = 0; e < D; ++e) u[e] = F[(PF_U0 + e) * NE];
     }
+    // Z = xi.u - |u|^2/2 at the face
+    __device__ __forceinline__ double z(const Vel& v) const {
+        double xu = 0.0;
+#pragma unroll
+        for (int e = 0; e < D; ++e) xu += v.xi[e] * u[e];
+        return xu - hu2;
+    }
     // phi at the face from phi_bar (eq. phibar inverted): g first, then b with
     // the S_b source at the face evaluated with the face g.
     __device__ __forceinline__ void invert(const Vel& v, double geq, double vg, double vb, double& gF,
                                            double& bF) const {
-        double xu = 0.0;
-#pragma unroll
-        for (int e = 0; e < D; ++e) xu += v.xi[e] * u[e];
+        invert_z(v, geq, z(v), vg, vb, gF, bF);
+    }
+    __device__ __forceinline__ void invert_z(const Vel& v, double geq, double Z, double vg, double vb, double& gF,
+                                             double& bF) const {
         double beq = (v.hx2 + cRT2) * geq;
-        double Z = xu - hu2;
         gF = geq + ig * (vg - geq);
         bF = beq + ib * (vb - beq) + eb * Z * (gF - geq);
     }
@@ -449,11 +456,11 @@ struct FaceCoef {
     }
     __device__ __forceinline__ void invert_accel(const Vel& v, double dt, double geq, double vg, double vb,
                                                  double& gF, double& bF) const {
-        double xu = 0.0;
-#pragma unroll
-        for (int e = 0; e < D; ++e) xu += v.xi[e] * u[e];
+        invert_accel_z(v, dt, geq, z(v), vg, vb, gF, bF);
+    }
+    __device__ __forceinline__ void invert_accel_z(const Vel& v, double dt, double geq, double Z, double vg,
+                                                   double vb, double& gF, double& bF) const {
         double beq = (v.hx2 + cRT2) * geq;
-        double Z = xu - hu2;
         const double c = c2 * (v.ax - au);
         gF = geq + ig * (vg - geq + c * geq);
         bF = beq + ib * (vb - beq + 0.25 * dt * v.ax * (gF - geq) + c * beq) + eb * Z * (gF - geq);
@@ -502,7 +509,17 @@ __device__ __forceinline__ double maxwellian_f32(double A, double s, const doubl
         const double x = v.xi[e] - u[e];
         c2 += x * x;
     }
-    const double t = fmax(-c2 * s * M_LOG2E, -1500.0);
+    const double t = fmin(fmax(-c2 * s * M_LOG2E, -1500.0), 1500.0);
+    const double n = rint(t);
+    return A * ldexp((double)__builtin_amdgcn_exp2f((float)(t - n)), (int)n);
+}
+// The same from Z = xi.u - |u|^2/2, which the face inversion and the S_b
+// source need anyway: |xi - u|^2 = 2 (|xi|^2/2 - Z), so the exponent takes one
+// subtraction instead of D differences and squares.  The rounding of the
+// expanded square (relative 1e-16 of |xi|^2 + |u|^2) stays far below the
+// FP32 accuracy of the result.
+__device__ __forceinline__ double maxwellian_f32z(double A, double s, double Z, double hx2) {
+    const double t = fmin(fmax(2.0 * M_LOG2E * s * (Z - hx2), -1500.0), 1500.0);
     const double n = rint(t);
     return A * ldexp((double)__builtin_amdgcn_exp2f((float)(t - n)), (int)n);
 }
@@ -1026,10 +1043,13 @@ struct UpdateKernel {
         }
         int ix = v0 % nvx;
         // Maxwellians without the recurrence: the FP64 exponential for FP64
-        // storage, FP32 accuracy for the FP32 forms
-        auto equilibrium = [](double A, double s, const double* u, const Vel& v) __attribute__((always_inline)) {
-            if constexpr (std::is_same<ST, double>::value) return maxwellian<D>(A, s, u, v);
-            else return maxwellian_f32<D>(A, s, u, v);
+        // storage; FP32 accuracy for the FP32 forms, from Z = xi.u - |u|^2/2,
+        // which the inversion and the S_b source use as well
+        constexpr bool FZ = !std::is_same<ST, double>::value;
+        auto equilibrium = [](double A, double s, const double* u, double Z, const Vel& v)
+                               __attribute__((always_inline)) {
+            if constexpr (FZ) return maxwellian_f32z(A, s, Z, v.hx2);
+            else return maxwellian<D>(A, s, u, v);
         };
 
         // One velocity of the slice; its rows (g, b in and out, and the 3-D
@@ -1067,30 +1087,38 @@ struct UpdateKernel {
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 const long long o = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch;
+                const double Zl = fcl[d].z(v), Zr = fcr[d].z(v);
                 const double eql = WALKER ? wl[d].template value<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v)
-                                          : equilibrium(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v);
+                                          : equilibrium(fcl[d].A, fcl[d].inv2RT, fcl[d].u, Zl, v);
                 const double eqr = WALKER ? wr[d].template value<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v)
-                                          : equilibrium(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v);
+                                          : equilibrium(fcr[d].A, fcr[d].inv2RT, fcr[d].u, Zr, v);
                 double gl, bl, gr, br;
                 if constexpr (ACC) {
-                    fcl[d].invert_accel(v, dt, eql, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl, bl);
-                    fcr[d].invert_accel(v, dt, eqr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr, br);
+                    fcl[d].invert_accel_z(v, dt, eql, Zl, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl,
+                                          bl);
+                    fcr[d].invert_accel_z(v, dt, eqr, Zr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr,
+                                          br);
                 } else {
-                    fcl[d].invert(v, eql, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl, bl);
-                    fcr[d].invert(v, eqr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr, br);
+                    fcl[d].invert_z(v, eql, Zl, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl, bl);
+                    fcr[d].invert_z(v, eqr, Zr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr, br);
                 }
                 const double sxd = v.xi[d] * P.inv_dx[d];
                 Fg += sxd * (gr - gl);
                 Fb += sxd * (br - bl);
             }
-            double xu0 = 0.0;
+            double xu0 = 0.0, xu1 = 0.0;
 #pragma unroll
-            for (int d = 0; d < D; ++d) xu0 += v.xi[d] * k0.u[d];
-            const double geq0 = WALKER ? w0.value<D>(k0.A, k0.inv2RT, k0.u, v) : equilibrium(k0.A, k0.inv2RT, k0.u, v);
-            const double beq0 = (v.hx2 + k0.cRT2) * geq0;
-            const double geq1 = WALKER ? w1.value<D>(k1.A, k1.inv2RT, k1.u, v) : equilibrium(k1.A, k1.inv2RT, k1.u, v);
-            const double beq1 = (v.hx2 + k1.cRT2) * geq1;
+            for (int d = 0; d < D; ++d) {
+                xu0 += v.xi[d] * k0.u[d];
+                xu1 += v.xi[d] * k1.u[d];
+            }
             const double Z0 = xu0 - k0.hu2;
+            const double geq0 =
+                WALKER ? w0.value<D>(k0.A, k0.inv2RT, k0.u, v) : equilibrium(k0.A, k0.inv2RT, k0.u, Z0, v);
+            const double beq0 = (v.hx2 + k0.cRT2) * geq0;
+            const double geq1 = WALKER ? w1.value<D>(k1.A, k1.inv2RT, k1.u, v)
+                                       : equilibrium(k1.A, k1.inv2RT, k1.u, xu1 - k1.hu2, v);
+            const double beq1 = (v.hx2 + k1.cRT2) * geq1;
             // eq. phiupdate with dt/(2 tau) = 2 beta and dt S_b = 4 eta Z (g - g_eq)
             double gn = g + 2.0 * k1.beta * geq1 + 2.0 * k0.beta * (geq0 - g) - dt * Fg;
             double bn = b + 2.0 * k1.betab * beq1 + 2.0 * k0.betab * (beq0 - b) - dt * Fb +
