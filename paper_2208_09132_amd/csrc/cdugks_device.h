@@ -200,6 +200,11 @@ __device__ __forceinline__ double slot_value(typename StoreT<ST>::R r, unsigned 
 struct Bf16Row {};
 template <typename E>
 struct RowIO {
+    using Raw = E;  // a loaded element, as held until used
+    __device__ static Raw raw(const void* base, long long off, long long c) {
+        return ((const E*)((const char*)base + off))[c];
+    }
+    __device__ static double val(Raw r) { return (double)r; }
     __device__ static double ld(const void* base, long long off, long long c) {
         return (double)((const E*)((const char*)base + off))[c];
     }
@@ -210,6 +215,11 @@ struct RowIO {
 };
 template <>
 struct RowIO<Bf16Row> {
+    using Raw = __bf16;
+    __device__ static Raw raw(const void* base, long long off, long long c) {
+        return ((const __bf16*)((const char*)base + off))[c];
+    }
+    __device__ static double val(Raw r) { return (double)(float)r; }
     __device__ static double ld(const void* base, long long off, long long c) {
         return (double)(float)((const __bf16*)((const char*)base + off))[c];
     }
@@ -1052,10 +1062,30 @@ struct UpdateKernel {
             else return maxwellian<D>(A, s, u, v);
         };
 
-        // One velocity of the slice; its rows (g, b in and out, and the 3-D
-        // quarter-step fields) hold elements of kind E and start `off` bytes
-        // into each state array.  Every storage form runs this one body.
-        auto velocity = [&](int i, long long off, auto kind) __attribute__((always_inline)) {
+        // The loads of one velocity: g and b of the cell, and the stored face
+        // values at its 2D faces ([d][left g, left b, right g, right b]).
+        auto load = [&](int i, long long off, auto kind, typename RowIO<decltype(kind)>::Raw& rg,
+                        typename RowIO<decltype(kind)>::Raw& rb, CT (&fv)[4 * D]) __attribute__((always_inline)) {
+            using IO = RowIO<decltype(kind)>;
+            rg = IO::raw(P.g_in, off, cc);
+            rb = IO::raw(P.b_in, off, cc);
+            const CT* const F = (const CT*)P.FV;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const long long o = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch;
+                fv[4 * d] = F[o + fl[d]];
+                fv[4 * d + 1] = F[o + fstride + fl[d]];
+                fv[4 * d + 2] = F[o + fr[d]];
+                fv[4 * d + 3] = F[o + fstride + fr[d]];
+            }
+        };
+        // One velocity of the slice from its loads; its rows (g, b in and
+        // out, and the 3-D quarter-step fields) hold elements of kind E and
+        // start `off` bytes into each state array.  Every storage form runs
+        // this one body.
+        auto velocity = [&](int i, long long off, auto kind, const typename RowIO<decltype(kind)>::Raw& rg,
+                            const typename RowIO<decltype(kind)>::Raw& rb, const CT (&fv)[4 * D])
+                            __attribute__((always_inline)) {
             using IO = RowIO<decltype(kind)>;
             const Vel v = load_vel(P.vel, i);
             if constexpr (WALKER) {
@@ -1081,26 +1111,24 @@ struct UpdateKernel {
                     }
                 }
             }
-            const double g = IO::ld(P.g_in, off, cc);
-            const double b = IO::ld(P.b_in, off, cc);
+            const double g = IO::val(rg);
+            const double b = IO::val(rb);
             double Fg = 0.0, Fb = 0.0;
 #pragma unroll
             for (int d = 0; d < D; ++d) {
-                const long long o = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch;
                 const double Zl = fcl[d].z(v), Zr = fcr[d].z(v);
                 const double eql = WALKER ? wl[d].template value<D>(fcl[d].A, fcl[d].inv2RT, fcl[d].u, v)
                                           : equilibrium(fcl[d].A, fcl[d].inv2RT, fcl[d].u, Zl, v);
                 const double eqr = WALKER ? wr[d].template value<D>(fcr[d].A, fcr[d].inv2RT, fcr[d].u, v)
                                           : equilibrium(fcr[d].A, fcr[d].inv2RT, fcr[d].u, Zr, v);
                 double gl, bl, gr, br;
+                const double flg = fv[4 * d], flb = fv[4 * d + 1], frg = fv[4 * d + 2], frb = fv[4 * d + 3];
                 if constexpr (ACC) {
-                    fcl[d].invert_accel_z(v, dt, eql, Zl, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl,
-                                          bl);
-                    fcr[d].invert_accel_z(v, dt, eqr, Zr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr,
-                                          br);
+                    fcl[d].invert_accel_z(v, dt, eql, Zl, flg, flb, gl, bl);
+                    fcr[d].invert_accel_z(v, dt, eqr, Zr, frg, frb, gr, br);
                 } else {
-                    fcl[d].invert_z(v, eql, Zl, ld<CT>(P.FV, o + fl[d]), ld<CT>(P.FV, o + fstride + fl[d]), gl, bl);
-                    fcr[d].invert_z(v, eqr, Zr, ld<CT>(P.FV, o + fr[d]), ld<CT>(P.FV, o + fstride + fr[d]), gr, br);
+                    fcl[d].invert_z(v, eql, Zl, flg, flb, gl, bl);
+                    fcr[d].invert_z(v, eqr, Zr, frg, frb, gr, br);
                 }
                 const double sxd = v.xi[d] * P.inv_dx[d];
                 Fg += sxd * (gr - gl);
@@ -1153,12 +1181,34 @@ struct UpdateKernel {
             }
         };
 
-        if constexpr (!StoreT<ST>::MIXED) {
-            // FP64 without the recurrence: two velocities per trip (twice the
-            // loads in flight per wave)
-            constexpr int UNROLL = std::is_same<ST, double>::value && !WALKER ? 2 : 1;
-#pragma unroll UNROLL
-            for (int i = v0; i < v1; ++i) velocity(i, (long long)i * P.pitch * (long long)sizeof(ST), ST{});
+        auto off_of = [&](int i) { return (long long)i * P.pitch * (long long)sizeof(ST); };
+        // FP64 in 1-D and 2-D has the registers to load a velocity ahead; the
+        // FP32 forms would lose a wave per SIMD (2-D) or spill (3-D)
+        constexpr bool AHEAD = std::is_same<ST, double>::value && D <= 2;
+        if constexpr (!StoreT<ST>::MIXED && !AHEAD) {
+            for (int i = v0; i < v1; ++i) {
+                typename RowIO<ST>::Raw rg, rb;
+                CT fv[4 * D];
+                load(i, off_of(i), ST{}, rg, rb, fv);
+                velocity(i, off_of(i), ST{}, rg, rb, fv);
+            }
+        } else if constexpr (!StoreT<ST>::MIXED) {
+            // The loads of velocity i+1 are issued before velocity i is
+            // processed, into the other of two named register sets (the loop
+            // is unrolled by two), so a register with a load in flight is
+            // never copied; the last trip re-reads its own velocity.
+            typename RowIO<ST>::Raw ga, ba, gb, bb;
+            CT fa[4 * D], fb[4 * D];
+            if (v0 < v1) load(v0, off_of(v0), ST{}, ga, ba, fa);
+            int i = v0;
+            for (; i + 1 < v1; i += 2) {
+                load(i + 1, off_of(i + 1), ST{}, gb, bb, fb);
+                velocity(i, off_of(i), ST{}, ga, ba, fa);
+                const int n2 = i + 2 < v1 ? i + 2 : i + 1;
+                load(n2, off_of(n2), ST{}, ga, ba, fa);
+                velocity(i + 1, off_of(i + 1), ST{}, gb, bb, fb);
+            }
+            if (i < v1) velocity(i, off_of(i), ST{}, ga, ba, fa);
         } else {
             // BF16-tail form: the row kind is uniform, so each velocity runs
             // the body for FP32 or BF16 rows; the FP32 rows of the slice
@@ -1167,13 +1217,23 @@ struct UpdateKernel {
             if constexpr (ROWS != 2) {
                 for (int i = v0; i < v1; ++i) {
                     const long long o = row_word(P, i);
-                    if (!(o & 1)) velocity(i, o, float{});
+                    if (!(o & 1)) {
+                        float rg, rb;
+                        CT fv[4 * D];
+                        load(i, o, float{}, rg, rb, fv);
+                        velocity(i, o, float{}, rg, rb, fv);
+                    }
                 }
             }
             if constexpr (ROWS != 1) {
                 for (int i = v0; i < v1; ++i) {
                     const long long o = row_word(P, i);
-                    if (o & 1) velocity(i, o & ~1LL, Bf16Row{});
+                    if (o & 1) {
+                        __bf16 rg, rb;
+                        CT fv[4 * D];
+                        load(i, o & ~1LL, Bf16Row{}, rg, rb, fv);
+                        velocity(i, o & ~1LL, Bf16Row{}, rg, rb, fv);
+                    }
                 }
             }
         }
