@@ -351,7 +351,12 @@ def test_zmarch_columns_equal_the_box_kernel_bitwise():
              ("outflow f32", dict(out, storage="f32"), (1, 7, 8, 9)), ("bf16 tails", bf, (1, 7, 9)),
              ("dirichlet f64", dirichlet, (1, 7)), ("dirichlet f32", dict(dirichlet, storage="f32"), (1, 7)),
              ("single slope", dict(out, reconstruction="single_slope"), (1, 7)),
-             ("acceleration", dict(dirichlet, accel=[0.3, -0.8, 0.5]), (1, 7))]
+             ("acceleration", dict(dirichlet, accel=[0.3, -0.8, 0.5]), (1, 7)),
+             # one and two cells along z: the column's rings wrap or clamp
+             # onto the same planes
+             ("one plane", wl.random_fourier(3, [9, 7, 1], [5, 5, 4], rng, amp=0.2, Kn=1e-2), (1, 7, 8, 9)),
+             ("two planes, outflow", dict(wl.random_fourier(3, [6, 11, 2], [4, 5, 5], rng, amp=0.2, Kn=1e-2),
+                                          bc=["periodic", "outflow", "outflow"]), (1, 7, 8, 9))]
     for name, p, shapes in cases:
         ref = None
         for k in shapes:
@@ -368,6 +373,17 @@ def test_zmarch_columns_equal_the_box_kernel_bitwise():
     # a column shape outside the default is refused for Dirichlet sides
     with pytest.raises(cd.CdugksError):
         cd.Solver(dict(dirichlet, face_tile=8))
+
+
+def test_3d_one_and_two_cells_along_z():
+    """3-D grids one and two cells thick along z (the z-marching column's
+    rings then hold wrapped or clamped copies of the same planes) against the
+    oracle."""
+    rng = wl.SplitMix64(45)
+    check_parity(wl.random_fourier(3, [9, 7, 1], [5, 5, 4], rng, amp=0.2, Kn=1e-2), 4, 1e-12)
+    q = wl.random_fourier(3, [6, 11, 2], [4, 5, 5], rng, amp=0.2, Kn=1e-2)
+    q["bc"] = ["periodic", "outflow", "outflow"]
+    check_parity(q, 4, 1e-12)
 
 
 def test_face_sum_tile_requests_outside_the_list_are_refused():
