@@ -149,13 +149,33 @@ __device__ __forceinline__ void state_st(const Problem& P, void* base, int i, lo
     }
 }
 
-// The fields of velocity i at NS source cells of one thread, with a single
-// format branch per velocity (the row kind is uniform); raw until slot_value.
-template <typename ST, int NS>
+// The fields of velocity i at NS source cells of one thread, raw until
+// slot_value.  The BF16-tail form has two ways to read a row whose kind is
+// uniform per velocity:
+//  WORDS: one 32-bit load per slot whatever the row's kind (element c of a
+//    BF16 row is a half of word c/2, which slot_value takes out), so no branch
+//    on the row kind stands between these loads and the values that use them
+//    (at a branch's join the compiler waits for every load in flight).  A
+//    BF16 row reserves an FP32 row's bytes, so the word of its last element
+//    lies inside the row.  For loops over velocities.
+//  !WORDS: 16-bit loads under a branch on the row kind (the value in the low
+//    half, as for an even cell), for a velocity fixed over the loop.
+template <typename ST, int NS, bool WORDS = true>
 __device__ __forceinline__ void load_slots(const Problem& P, const void* sg, const void* sb, int i,
                                            const long long (&src)[NS], typename StoreT<ST>::R (&og)[NS],
                                            typename StoreT<ST>::R (&ob)[NS]) {
-    if constexpr (StoreT<ST>::MIXED) {
+    if constexpr (StoreT<ST>::MIXED && WORDS) {
+        const long long o = row_word(P, i);
+        const int h = (int)(o & 1);
+        const unsigned* rg = (const unsigned*)((const char*)sg + (o & ~1LL));
+        const unsigned* rb = (const unsigned*)((const char*)sb + (o & ~1LL));
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const long long w = src[k] >> h;
+            og[k] = rg[w];
+            ob[k] = rb[w];
+        }
+    } else if constexpr (StoreT<ST>::MIXED) {
         const long long o = row_word(P, i);
         const char* rg = (const char*)sg + (o & ~1LL);
         const char* rb = (const char*)sb + (o & ~1LL);
@@ -185,11 +205,17 @@ __device__ __forceinline__ void load_slots(const Problem& P, const void* sg, con
         }
     }
 }
-// value of a raw slot; shift = 16 for a BF16 row, else 0 (uniform)
+// value of a raw slot of cell c: in a BF16 row (half, uniform) a word loaded
+// by WORDS holds cells c and c ^ 1, the odd cell in the upper half; a 16-bit
+// load is passed as an even cell
 template <typename ST>
-__device__ __forceinline__ double slot_value(typename StoreT<ST>::R r, unsigned shift) {
-    if constexpr (StoreT<ST>::MIXED) return (double)__uint_as_float(r << shift);
-    else return (double)r;
+__device__ __forceinline__ double slot_value(typename StoreT<ST>::R r, bool half, long long c) {
+    if constexpr (StoreT<ST>::MIXED) {
+        const unsigned bits = half ? ((c & 1) ? (r & 0xFFFF0000u) : (r << 16)) : r;
+        return (double)__uint_as_float(bits);
+    } else {
+        return (double)r;
+    }
 }
 
 // Access within one velocity row of the update kernel, whose element kind is
@@ -761,7 +787,7 @@ struct FaceSumKernel {
                 }
             }
             // BF16 rows: the raw halves move to the top of an FP32 word
-            const unsigned shift = StoreT<ST>::MIXED ? (unsigned)(row_word(P, i) & 1) << 4 : 0u;
+            const bool half = StoreT<ST>::MIXED && (row_word(P, i) & 1);
             CT* const sq0 = sm.q[buf][0];
             CT* const sq1 = sm.q[buf][1];
             CT* const sa0 = sm.a[buf][0];
@@ -780,8 +806,8 @@ struct FaceSumKernel {
                     const int r = lq[k] & 0xFFFFF;
                     double g, b;
                     if constexpr (PREFETCH) {
-                        g = slot_value<ST>(cur_g[k], shift);
-                        b = slot_value<ST>(cur_b[k], shift);
+                        g = slot_value<ST>(cur_g[k], half, srcq[k]);
+                        b = slot_value<ST>(cur_b[k], half, srcq[k]);
                     } else {
                         g = state_ld<ST>(P, src_g, i, srcq[k]);
                         b = state_ld<ST>(P, src_b, i, srcq[k]);
@@ -1324,6 +1350,7 @@ struct ZMarch {
     static constexpr int AX = TX + 3, AY = TY + 3, NA = AX * AY;  // difference plane
     static constexpr int NSLOT = (NQ + NT - 1) / NT;              // q points per thread
     static constexpr int NPASS = (2 * NA + NTH - 1) / NTH;        // (point, field) passes
+    static_assert(NF == 1 || !StoreT<ST>::MIXED, "the BF16-tail form loads its rows through load_slots");
     struct Smem {
         CT q[4][2][NQ];
         CT a[2][2][3][NA];  // [ring][field][component][point]
@@ -1359,7 +1386,7 @@ struct ZMarch {
             }
         }
         const Vel v = load_vel(P.vel, i);
-        const unsigned shift = StoreT<ST>::MIXED ? (unsigned)(row_word(P, i) & 1) << 4 : 0u;
+        const bool half = StoreT<ST>::MIXED && (row_word(P, i) & 1);
 
         // raw fields of the next plane to stage: both, or the thread's one
         RT pg[NSLOT], pb[NSLOT];
@@ -1369,7 +1396,7 @@ struct ZMarch {
 #pragma unroll
             for (int k = 0; k < NSLOT; ++k) src[k] = base + off[k];
             if constexpr (NF == 1) {
-                load_slots<ST, NSLOT>(P, P.qg, P.qb, i, src, pg, pb);
+                load_slots<ST, NSLOT, false>(P, P.qg, P.qb, i, src, pg, pb);
             } else {
                 const void* const q = f0 ? P.qb : P.qg;
 #pragma unroll
@@ -1388,7 +1415,7 @@ struct ZMarch {
 #pragma unroll
                 for (int j = 0; j < FL; ++j) {
                     const int f = f0 + j;
-                    double val = slot_value<ST>(j == 0 ? pg[k] : pb[k], shift);
+                    double val = slot_value<ST>(j == 0 ? pg[k] : pb[k], half, 0);
                     if constexpr (DIR) {
                         const int side = zs ? zs : sxy[k];
                         if (side) val = P.dir_eq[((long long)(side - 1) * P.V + i) * 2 + f];
