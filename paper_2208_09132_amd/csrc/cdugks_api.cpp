@@ -271,7 +271,10 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
     // at power-of-two distances the same cells of consecutive velocity rows
     // contend for the same memory channels (3-D FP32 face sums 48 -> 33 ms).
     r.pitch = (long long)row_pitch_bytes((size_t)r.N * es) / (long long)es;
-    r.fv_pitch = (long long)row_pitch_bytes((size_t)r.NE * es, FV_ROW_PAD) / (long long)es;
+    // one spare element per face-value row: the face-sum kernels store the
+    // values of faces outside the grid there, so their stores are
+    // unconditional (no branch before the next velocity's loads are used)
+    r.fv_pitch = (long long)row_pitch_bytes((size_t)(r.NE + 1) * es, FV_ROW_PAD) / (long long)es;
     const size_t state_bytes = r.storage == CDUGKS_STORE_F32_BF16TAIL
                                    ? (size_t)r.V * row_pitch_bytes((size_t)r.N * 4)
                                    : (size_t)r.V * (size_t)r.pitch * es;

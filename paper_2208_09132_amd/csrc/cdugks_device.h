@@ -155,9 +155,10 @@ __device__ __forceinline__ void state_st(const Problem& P, void* base, int i, lo
 //  WORDS: one 32-bit load per slot whatever the row's kind (element c of a
 //    BF16 row is a half of word c/2, which slot_value takes out), so no branch
 //    on the row kind stands between these loads and the values that use them
-//    (at a branch's join the compiler waits for every load in flight).  A
-//    BF16 row reserves an FP32 row's bytes, so the word of its last element
-//    lies inside the row.  For loops over velocities.
+//    (at a branch's join the compiler waits for every load in flight).  The
+//    word of a BF16 row's last element reaches past the row's 2N bytes only
+//    for an odd N, into the padding that rounds the row to 256 bytes.  For
+//    loops over velocities.
 //  !WORDS: 16-bit loads under a branch on the row kind (the value in the low
 //    half, as for an even cell), for a velocity fixed over the loop.
 template <typename ST, int NS, bool WORDS = true>
@@ -664,7 +665,7 @@ struct FaceSumKernel {
     static constexpr int NBUF = D <= 2 ? 2 : 1;
 
     struct Smem {
-        CT q[NBUF][2][G::NQ];      // phi_bar_plus for g, b
+        CT q[NBUF][2][G::NQ + 1];  // phi_bar_plus for g, b (entry NQ: unused slots)
         CT a[NBUF][2][D * G::NA];  // limited differences for g, b
     };
 
@@ -799,11 +800,14 @@ struct FaceSumKernel {
                 load_slots<ST, NSLOT>(P, src_g, src_b, i + 1 < v1 ? i + 1 : i, srcq, nxt_g, nxt_b);
             }
 
-            // stage 1: quarter-step fields on the q box
+            // stage 1: quarter-step fields on the q box; a slot without a
+            // point (the last ones of the halo) computes from cell 0 and
+            // writes LDS entry NQ, which nothing reads, so the loop has no
+            // branch between the loads of the previous velocity and their use
 #pragma unroll
             for (int k = 0; k < NSLOT; ++k) {
-                if (lq[k] >= 0) {
-                    const int r = lq[k] & 0xFFFFF;
+                {
+                    const int r = lq[k] >= 0 ? (lq[k] & 0xFFFFF) : G::NQ;
                     double g, b;
                     if constexpr (PREFETCH) {
                         g = slot_value<ST>(cur_g[k], half, srcq[k]);
@@ -821,7 +825,7 @@ struct FaceSumKernel {
                         quarter_step_eq<D, ACC>(kq[k], v, geq, g, b, qg, qb, &P);
                     }
                     if constexpr (DIR) {
-                        if (lq[k] >> 20) {  // Dirichlet ghost: the fixed state's equilibrium
+                        if (lq[k] > 0 && (lq[k] >> 20)) {  // Dirichlet ghost: the fixed state's equilibrium
                             const double* de = P.dir_eq + ((long long)((lq[k] >> 20) - 1) * P.V + i) * 2;
                             qg = de[0];
                             qb = de[1];
@@ -865,7 +869,7 @@ struct FaceSumKernel {
                     const int p = slope_ring_point(h);
                     const int px = p % G::AX, py = (p / G::AX) % G::AY, pz = p / (G::AX * G::AY);
                     const int qi = (px + 1) + G::QX * ((py + (D >= 2 ? 1 : 0)) + G::QY * (pz + (D >= 3 ? 1 : 0)));
-                    const CT* q = sq0 + f * G::NQ;
+                    const CT* q = f == 0 ? sq0 : sq1;
                     CT* a = sa0 + f * (D * G::NA);
                     const CT c = q[qi];
 #pragma unroll
@@ -935,8 +939,12 @@ struct FaceSumKernel {
                     fv[1] = CT(0.5) * (left_value(1) + right_value(1));
                 }
                 const double vg = fv[0], vb2 = fv[1];
-                if (fvalid[d]) {
-                    const long long o = (long long)(2 * d) * fstride + (long long)i * P.fv_pitch + fe;
+                {
+                    // a face outside the grid goes to the row's spare element
+                    // NE: with the store unconditional the compiler need not
+                    // wait for it before using the next velocity's loads
+                    const long long o =
+                        (long long)(2 * d) * fstride + (long long)i * P.fv_pitch + (fvalid[d] ? fe : NE);
                     st_stream<CT>(P.FV, o, vg);
                     st_stream<CT>(P.FV, o + fstride, vb2);
                 }
@@ -963,12 +971,17 @@ struct FaceSumKernel {
         };
 
         if constexpr (D <= 2) {
+            // The first velocity is peeled off, so the loop is entered, like
+            // its back edge, with a velocity's face-value stores in flight:
+            // the compiler's wait counts at the loop head then need not wait
+            // for those stores before the fields loaded ahead are used.
             int i = v0;
+            if (i < v1) velocity(i++, 0, pa_g, pa_b, pb_g, pb_b);
             for (; i + 1 < v1; i += 2) {
-                velocity(i, 0, pa_g, pa_b, pb_g, pb_b);
-                velocity(i + 1, NBUF - 1, pb_g, pb_b, pa_g, pa_b);
+                velocity(i, NBUF - 1, pb_g, pb_b, pa_g, pa_b);
+                velocity(i + 1, 0, pa_g, pa_b, pb_g, pb_b);
             }
-            if (i < v1) velocity(i, 0, pa_g, pa_b, pb_g, pb_b);
+            if (i < v1) velocity(i, NBUF - 1, pb_g, pb_b, pa_g, pa_b);
         } else {
             // 3-D: registers allow one set; the copy costs a wait per velocity
             for (int i = v0; i < v1; ++i) {
@@ -1522,8 +1535,11 @@ struct ZMarch {
 #pragma unroll
                         for (int j = 0; j < FL; ++j) fv[j] = CT(0.5) * (left_value(j) + right_value(j));
                     }
-                    if (valid) {
-                        const long long o = (long long)(2 * d + f0) * fstride + (long long)i * P.fv_pitch + fe;
+                    {
+                        // a face outside the grid goes to the row's spare
+                        // element NE (the store stays unconditional)
+                        const long long o = (long long)(2 * d + f0) * fstride + (long long)i * P.fv_pitch +
+                                            (valid ? fe : P.NE);
 #pragma unroll
                         for (int j = 0; j < FL; ++j) st_stream<CT>(P.FV, o + j * fstride, fv[j]);
                     }

@@ -190,8 +190,8 @@ constexpr int tile_threads(int D, int id) {
     return tile_shape(D, id).x * tile_shape(D, id).y * (tile_zmarch(D, id) ? 1 : tile_shape(D, id).z);
 }
 // Static LDS of a face-sum workgroup (element size es of the stencil
-// arithmetic).  Box shapes: q box and limited-difference box for g and b,
-// double-buffered in 1-D and 2-D.  z-marching columns: a ring of four q
+// arithmetic).  Box shapes: q box (plus one entry for unused slots) and
+// limited-difference box for g and b, double-buffered in 1-D and 2-D.  z-marching columns: a ring of four q
 // planes and a ring of two planes of the three limited differences.  Shapes
 // whose LDS exceeds the 160 KB of a CU do not exist for that storage form.
 constexpr long long face_sum_lds_bytes(int D, int id, int es) {
@@ -200,7 +200,7 @@ constexpr long long face_sum_lds_bytes(int D, int id, int es) {
     const long long ax = t.x + 3, ay = D >= 2 ? t.y + 3 : 1, az = D >= 3 ? t.z + 3 : 1;
     if (tile_zmarch(D, id)) return 2LL * es * (4 * qx * qy + 2 * 3 * ax * ay);
     const long long nbuf = D <= 2 ? 2 : 1;
-    return nbuf * 2 * es * (qx * qy * qz + D * ax * ay * az);
+    return nbuf * 2 * es * (qx * qy * qz + 1 + D * ax * ay * az);
 }
 constexpr long long LDS_PER_CU = 160 * 1024;
 constexpr bool face_tile_fits(int D, int id, int es) { return face_sum_lds_bytes(D, id, es) <= LDS_PER_CU; }
