@@ -91,7 +91,7 @@ struct WorkItem {
     int prob;     // index into the problem table
     int tile;     // face sums: linear tile index; update: block of 256 cells
     int slice;    // velocity slice
-    int pad;
+    int nslices;  // update items: the problem's velocity slices in this batch (face items: unused)
 };
 
 // Launchers (stream-ordered).  Single-problem forms take the descriptor by

@@ -125,9 +125,9 @@ __global__ __launch_bounds__(WG) void k_update_batched(const Problem* probs, con
         const WorkItem it = load_uniform(items + w);
         const Problem P = load_uniform(probs + it.prob);
         const long long c = (long long)it.tile * WG + threadIdx.x;
-        if (P.D == 1) UpdateKernel<1, ST>::run(P, c, it.slice, P.nslices_upd);
-        else if (MAXD >= 2 && P.D == 2) UpdateKernel<MAXD >= 2 ? 2 : 1, ST>::run(P, c, it.slice, P.nslices_upd);
-        else if (MAXD >= 3) UpdateKernel<MAXD >= 3 ? 3 : 1, ST>::run(P, c, it.slice, P.nslices_upd);
+        if (P.D == 1) UpdateKernel<1, ST>::run(P, c, it.slice, it.nslices);
+        else if (MAXD >= 2 && P.D == 2) UpdateKernel<MAXD >= 2 ? 2 : 1, ST>::run(P, c, it.slice, it.nslices);
+        else if (MAXD >= 3) UpdateKernel<MAXD >= 3 ? 3 : 1, ST>::run(P, c, it.slice, it.nslices);
     }
 }
 

@@ -192,6 +192,18 @@ void batch_free(cdugks_batch* b) {
     delete b;
 }
 
+// Velocity slices of a problem's update items in a batch: at least
+// BATCH_UPD_VELOCITIES velocities per item (all of them for smaller velocity
+// sets), never more slices than the problem's own plan.
+#ifndef CDG_BATCH_UPD_VELOCITIES
+#define CDG_BATCH_UPD_VELOCITIES 256
+#endif
+constexpr int BATCH_UPD_VELOCITIES = CDG_BATCH_UPD_VELOCITIES;
+int batch_update_slices(const Resolved& r) {
+    const long long s = std::max(1LL, r.V / BATCH_UPD_VELOCITIES);
+    return (int)std::min<long long>(s, std::max(1, r.nslices_upd));
+}
+
 // Build device tables for a set of contexts.
 int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batch** out) {
     if (!out) return fail(CDUGKS_ERR_INVALID, "null output pointer");
@@ -263,11 +275,17 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
                 fs[s].push_back(WorkItem{j, t, sl, 0});
                 cfs[s].push_back(vpt * r.D * (r.D + 1));
             }
+        // Update items take the batch's own velocity split: the update forms
+        // no sums, so its split never changes a result, and the batch has
+        // work enough to fill the device without the many short slices a
+        // small problem uses alone, each of which loads the cell's and its
+        // faces' coefficient sets again.
         const int nb = (int)((r.N + 255) / 256);
-        const double vpu = (double)r.V / r.nslices_upd;
-        for (int sl = 0; sl < r.nslices_upd; ++sl)
+        const int us = batch_update_slices(r);
+        const double vpu = (double)r.V / us;
+        for (int sl = 0; sl < us; ++sl)
             for (int t = 0; t < nb; ++t) {
-                up[s].push_back(WorkItem{j, t, sl, 0});
+                up[s].push_back(WorkItem{j, t, sl, us});
                 cup[s].push_back(vpu * r.D);
             }
     }
