@@ -715,7 +715,12 @@ struct FaceSumKernel {
                 int cy = D >= 2 ? map_coord(c3[1], P.n[1], P.bc[1]) : 0;
                 int cz = D >= 3 ? map_coord(c3[2], P.n[2], P.bc[2]) : 0;
                 srcq[k] = cx + (long long)P.n[0] * (cy + (long long)P.n[1] * cz);
-                if constexpr (KQ) kq[k] = load_coef(P.P_in, N, srcq[k]);
+            }
+            // every slot's coefficients, an unused slot's those of cell 0:
+            // stage 1 evaluates each slot (its result unread for an unused one)
+            if constexpr (KQ) {
+#pragma unroll
+                for (int k = 0; k < NSLOT; ++k) kq[k] = load_coef(P.P_in, N, srcq[k]);
             }
         }
         // own cell = the left faces this thread reconstructs

@@ -192,14 +192,13 @@ void batch_free(cdugks_batch* b) {
     delete b;
 }
 
-// Velocity slices of a problem's update items in a batch: at least
-// BATCH_UPD_VELOCITIES velocities per item (all of them for smaller velocity
-// sets), never more slices than the problem's own plan.
-#ifndef CDG_BATCH_UPD_VELOCITIES
-#define CDG_BATCH_UPD_VELOCITIES 256
-#endif
-constexpr int BATCH_UPD_VELOCITIES = CDG_BATCH_UPD_VELOCITIES;
+// Velocity slices of a problem's update items in a batch: the autotuner's
+// split for the problem's class when it has one (its trials time this very
+// path), else at least BATCH_UPD_VELOCITIES velocities per item (all of them
+// for smaller velocity sets), never more slices than the problem's own plan.
+constexpr int BATCH_UPD_VELOCITIES = 256;
 int batch_update_slices(const Resolved& r) {
+    if (const int tu = tune_lookup(r).upd_slices; tu > 0) return (int)std::min<long long>(tu, r.V);
     const long long s = std::max(1LL, r.V / BATCH_UPD_VELOCITIES);
     return (int)std::min<long long>(s, std::max(1, r.nslices_upd));
 }
@@ -752,7 +751,6 @@ int cdugks_autotune(cdugks_ctx* c, int steps_per_trial) {
     int best_s = base, best_g = 1;
     double best_t = 1e300;
     const Resolved saved = c->r;
-    const Problem savedP = c->P;
     int rc = CDUGKS_OK;
     for (int gf = 1; gf <= 2 && rc == CDUGKS_OK; ++gf) {
         for (int k = 0; k < 4 && rc == CDUGKS_OK; ++k) {
