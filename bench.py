@@ -336,8 +336,8 @@ def main():
                     help="also run the library's FP64 distribution copy (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design note, "
-              "not a code path (use --gpus 1)", file=sys.stderr)
+        print("bench.py: the library steps a problem on one GPU; sharding over several GPUs is "
+              "described in the design notes but not implemented (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
