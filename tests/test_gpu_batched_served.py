@@ -166,6 +166,18 @@ def test_autotune_keeps_results():
         for x, y in zip(ref2, t.moments()):
             assert np.array_equal(x, y)
         t.close()
+        # a batch whose update items take the split tuned for this class
+        solvers = [cd.Solver(p), cd.Solver(mixed_problems(seed=5, count=2)[1])]
+        ref3 = alone(solvers[1].prob, 6)
+        b = cd.Batch(solvers, chunk_steps=4)
+        b.step(6)
+        b.close()
+        for x, y in zip(ref, solvers[0].moments()):
+            assert np.array_equal(x, y)
+        for x, y in zip(ref3, solvers[1].moments()):
+            assert np.array_equal(x, y)
+        for sv in solvers:
+            sv.close()
 
 
 def test_server_results_equal_alone_and_budget_admission():
