@@ -98,6 +98,24 @@ def test_sizes_beyond_the_index_ranges_are_rejected():
         assert "too large" in str(ei.value)
 
 
+def test_degenerate_descriptions_are_rejected():
+    """Empty grids (no cells along an axis), fewer than two velocities on an
+    axis, an empty domain or velocity box and an unsupported dimension are
+    refused with ERR_INVALID before anything is allocated."""
+    base = {"dim": 1, "n": [128], "lo": [0.0], "hi": [1.0], "bc": ["periodic"], "nv": [16], "vmin": [-6.0],
+            "vmax": [6.0], "relax": "mu", "mu_ref": 1e-3}
+    three = {"dim": 3, "n": [4, 4, 4], "lo": [0.0] * 3, "hi": [1.0] * 3, "bc": ["periodic"] * 3, "nv": [4, 4, 4],
+             "vmin": [-6.0] * 3, "vmax": [6.0] * 3, "relax": "mu", "mu_ref": 1e-3}
+    bad = [dict(base, n=[0]), dict(base, n=[-3]), dict(base, nv=[1]), dict(base, nv=[0]), dict(base, hi=[0.0]),
+           dict(base, vmax=[-6.0]), dict(base, dim=0), dict(three, n=[4, 4, 0]), dict(three, nv=[4, 1, 4])]
+    for p in bad:
+        with pytest.raises(cd.CdugksError) as ei:
+            cd.cdugks_required_bytes(p)
+        assert ei.value.code == cd.ERR_INVALID
+    # the smallest accepted: one cell, two velocities
+    assert cd.cdugks_required_bytes(dict(base, n=[1], nv=[2])) > 0
+
+
 def test_long_velocity_axes_are_accepted():
     """One axis may carry up to 2^24 - 1 velocities (the Sec. 3 sine-wave
     problem uses 16385); the total count and the product with the cells are

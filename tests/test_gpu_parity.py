@@ -386,6 +386,23 @@ def test_3d_one_and_two_cells_along_z():
     check_parity(q, 4, 1e-12)
 
 
+def test_smallest_grids():
+    """The smallest problems the library accepts: one cell (periodic, where
+    every neighbour is the cell itself, and outflow), single-cell axes in 2-D
+    and 3-D, two velocities per axis; FP64 against the oracle at 1e-12, the
+    FP32 form at 1e-5."""
+    rng = wl.SplitMix64(46)
+    cases = [(1, [1], [2], ["periodic"]), (1, [1], [3], ["outflow"]),
+             (2, [1, 3], [2, 3], ["outflow", "periodic"]), (2, [2, 1], [3, 2], ["periodic", "periodic"]),
+             (3, [2, 1, 3], [2, 3, 2], ["outflow", "periodic", "periodic"])]
+    for dim, n, nv, bc in cases:
+        p = wl.random_fourier(dim, n, nv, rng, amp=0.2, Kn=1e-1)
+        p["bc"] = bc
+        check_parity(p, 5, 1e-12)
+    q = wl.random_fourier(2, [1, 3], [2, 3], rng, amp=0.2, Kn=1e-1, storage="f32")
+    check_parity(q, 5, 1e-5)
+
+
 def test_face_sum_tile_requests_outside_the_list_are_refused():
     p = wl.kelvin_helmholtz(n=24, nv=8)
     for bad in (-1, 5):
