@@ -389,18 +389,32 @@ def test_3d_one_and_two_cells_along_z():
 def test_smallest_grids():
     """The smallest problems the library accepts: one cell (periodic, where
     every neighbour is the cell itself, and outflow), single-cell axes in 2-D
-    and 3-D, two velocities per axis; FP64 against the oracle at 1e-12, the
-    FP32 form at 1e-5."""
+    and 3-D, two velocities per axis (on [-1.5, 1.5], so that the coarse
+    velocity grids still carry transport).  Moments in FP64 against the
+    oracle at 1e-12 and the FP32 form at 1e-5; a single cell has no gradient,
+    so its moments stay put, and its g and b, which still relax, are compared
+    element by element."""
+    from tests.test_gpu_distributions import check_distributions
+
     rng = wl.SplitMix64(46)
-    cases = [(1, [1], [2], ["periodic"]), (1, [1], [3], ["outflow"]),
-             (2, [1, 3], [2, 3], ["outflow", "periodic"]), (2, [2, 1], [3, 2], ["periodic", "periodic"]),
-             (3, [2, 1, 3], [2, 3, 2], ["outflow", "periodic", "periodic"])]
-    for dim, n, nv, bc in cases:
-        p = wl.random_fourier(dim, n, nv, rng, amp=0.2, Kn=1e-1)
-        p["bc"] = bc
-        check_parity(p, 5, 1e-12)
-    q = wl.random_fourier(2, [1, 3], [2, 3], rng, amp=0.2, Kn=1e-1, storage="f32")
-    check_parity(q, 5, 1e-5)
+
+    def small(dim, n, nv, bc, storage="f64"):
+        p = wl.random_fourier(dim, n, nv, rng, amp=0.2, Kn=1e-1, storage=storage)
+        p["bc"], p["vmin"], p["vmax"] = bc, [-1.5] * dim, [1.5] * dim
+        return p
+
+    for dim, n, nv, bc in [(1, [2], [2], ["periodic"]), (2, [1, 3], [2, 3], ["outflow", "periodic"]),
+                           (2, [2, 1], [3, 2], ["periodic", "periodic"]),
+                           (3, [2, 1, 3], [2, 3, 2], ["outflow", "periodic", "periodic"])]:
+        check_parity(small(dim, n, nv, bc), 5, 1e-12)
+    check_parity(small(2, [1, 3], [2, 3], ["periodic", "periodic"], "f32"), 5, 1e-5)
+    for bc in ("periodic", "outflow"):
+        p = small(1, [1], [3], [bc])
+        start, _ = gpu_run(p, 0)
+        got, _ = gpu_run(p, 5)
+        for a, b in zip(got, start):
+            assert np.array_equal(a, b)
+        check_distributions(p)
 
 
 def test_face_sum_tile_requests_outside_the_list_are_refused():
