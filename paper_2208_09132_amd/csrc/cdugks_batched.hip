@@ -4,12 +4,19 @@
 
 namespace cdg {
 
+// waves per SIMD the batched face sums are compiled for: 3 for the FP32
+// forms of 1-D and 2-D classes, like the single-problem 2-D kernel
+template <typename ST, int MAXD>
+constexpr int batched_face_waves() { return MAXD <= 2 && !std::is_same<ST, double>::value ? 3 : 1; }
+
 template <typename ST, int MAXD, bool DIR, bool SS>
-__global__ __launch_bounds__(WG) void k_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems,
+__global__ __launch_bounds__(WG, (batched_face_waves<ST, MAXD>())) void k_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems,
                                                           int* queue, int* other) {
+    // 2-D problems in the batched tile shape of the storage form
+    constexpr int T2 = MAXD >= 2 ? batched_face_tile(2, std::is_same<ST, double>::value ? 0 : 1) : 0;
     __shared__ union U {
         typename FaceSumKernel<1, ST, DIR, SS>::Smem s1;
-        typename FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR, SS>::Smem s2;
+        typename FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR, SS, T2>::Smem s2;
         typename FaceSumKernel<MAXD >= 3 ? 3 : 1, ST, DIR, SS>::Smem s3;
     } sm;
     __shared__ int slot;
@@ -19,7 +26,7 @@ __global__ __launch_bounds__(WG) void k_face_sums_batched(const Problem* probs, 
         const Problem P = load_uniform(probs + it.prob);
         if (P.D == 1) FaceSumKernel<1, ST, DIR, SS>::run(P, it.tile, it.slice, P.nslices, sm.s1);
         else if (MAXD >= 2 && P.D == 2)
-            FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR, SS>::run(P, it.tile, it.slice, P.nslices, sm.s2);
+            FaceSumKernel<MAXD >= 2 ? 2 : 1, ST, DIR, SS, T2>::run(P, it.tile, it.slice, P.nslices, sm.s2);
         else if (MAXD >= 3)
             FaceSumKernel<MAXD >= 3 ? 3 : 1, ST, DIR, SS>::run(P, it.tile, it.slice, P.nslices, sm.s3);
     }

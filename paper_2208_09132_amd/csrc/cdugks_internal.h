@@ -185,6 +185,12 @@ constexpr TileExt tile_shape(int D, int id) {
     }
 }
 constexpr bool tile_zmarch(int D, int id) { return D == 3 && tile_shape(D, id).z == 0; }
+// Tile shape of batched face-sum launches.  The FP32 forms of 2-D problems
+// take 32 x 8: a 16-wide tile row of FP32 face values or fields is half a
+// 128-byte line, whose other half belongs to a tile that in a batch seldom
+// runs beside it on the same XCD, so half of each line fetched would be
+// wasted.  Every shape gives the same results.
+constexpr int batched_face_tile(int D, int storage) { return D == 2 && storage != 0 ? 1 : 0; }
 constexpr int default_face_tile(int D) { return D == 3 ? 6 : 0; }
 constexpr int tile_threads(int D, int id) {
     return tile_shape(D, id).x * tile_shape(D, id).y * (tile_zmarch(D, id) ? 1 : tile_shape(D, id).z);

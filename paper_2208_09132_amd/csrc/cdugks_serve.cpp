@@ -192,6 +192,13 @@ void batch_free(cdugks_batch* b) {
     delete b;
 }
 
+// Tiles along axis d of a problem in the batched tile shape.
+int batched_tiles(const Resolved& r, int d) {
+    const TileExt t = tile_shape(r.D, batched_face_tile(r.D, r.storage));
+    const int te[3] = {t.x, t.y, t.z};
+    return (r.ne[d] + te[d] - 1) / te[d];
+}
+
 // Velocity slices of a problem's update items in a batch: the autotuner's
 // split for the problem's class when it has one (its trials time this very
 // path), else at least BATCH_UPD_VELOCITIES velocities per item (all of them
@@ -242,10 +249,10 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
         for (int p = 0; p < 2; ++p) {
             Problem P = c->P;
             set_pingpong(P, c->r, c->base, c->cur ^ p);
-            // batched launches run the default tile shape of each dimension
-            // (the same result as any other shape)
-            P.tile = 0;
-            for (int d = 0; d < 3; ++d) P.tiles1[d] = c->r.tiles1_def[d];
+            // batched launches run the batched tile shape of the problem's
+            // dimension and storage form (the same result as any other shape)
+            P.tile = batched_face_tile(c->r.D, c->r.storage);
+            for (int d = 0; d < 3; ++d) P.tiles1[d] = batched_tiles(c->r, d);
             probs[p].push_back(P);
         }
         face_off[j] = ft;
@@ -267,7 +274,7 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
         const Resolved& r = ctxs[j]->r;
         const int s = class_of(r);
         maxd[s] = std::max(maxd[s], r.D);
-        const int nt = r.tiles1_def[0] * r.tiles1_def[1] * r.tiles1_def[2];
+        const int nt = batched_tiles(r, 0) * batched_tiles(r, 1) * batched_tiles(r, 2);
         const double vpt = (double)r.V / r.nslices;
         for (int sl = 0; sl < r.nslices; ++sl)
             for (int t = 0; t < nt; ++t) {
