@@ -15,7 +15,7 @@ struct Resolved {
     int D;
     int n[3], ne[3], bc[3], nv[3];
     int tiles1[3];      // face-sum tiles per dimension for the chosen shape
-    int tiles1_def[3];  // ... and for the default shape (batched launches, slice plan)
+    int tiles1_def[3];  // ... and for shape 0 (the velocity-slice plan)
     int tile;           // face-sum tile shape (index into tile_shape(D, .))
     long long N, NE, V;
     double dx[3];

@@ -144,8 +144,9 @@ hipError_t launch_cell_close_batched(const Problem* probs, const long long* offs
 int tile_blocks_per_cu(int D, int storage, bool update);
 
 // Face-sum tile shapes: cells per workgroup along x, y, z, one thread per
-// cell.  Shape 0 of each dimension plans the velocity split and is the shape
-// of batched launches; default_face_tile(D) is the one a single problem runs
+// cell.  Shape 0 of each dimension plans the velocity split;
+// batched_face_tile(D, storage) is the shape of batched launches and
+// default_face_tile(D) the one a single problem runs
 // unless the caller (cdugks_params.face_tile) or the autotuner chooses
 // another.  A cell's arithmetic does not depend on the tile it sits in (in
 // 2-D every shape keeps its q-box slots in registers, see Geo), and the
