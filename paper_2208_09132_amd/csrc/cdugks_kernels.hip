@@ -140,20 +140,24 @@ __global__ __launch_bounds__(WG) void k_cell_close(Problem P) {
 }
 
 
+// Batched closures: every problem's range of threads starts on a workgroup
+// boundary (offsets in threads, multiples of WG), so a workgroup serves one
+// problem, found once per workgroup (its descriptor then read at one address
+// by every lane); threads past the problem's faces (cells) return.
 __global__ __launch_bounds__(WG) void k_face_close_batched(const Problem* probs, const long long* offsets,
                                                            int nprob, long long total) {
-    long long g = (long long)blockIdx.x * WG + threadIdx.x;
-    if (g >= total) return;
-    int p = find_problem(offsets, nprob, g);
-    face_close_one(probs[p], g - offsets[p]);  // by reference: no private copy
+    const long long g0 = (long long)blockIdx.x * WG;
+    if (g0 >= total) return;
+    const int p = __builtin_amdgcn_readfirstlane(find_problem(offsets, nprob, g0));
+    face_close_one(probs[p], g0 - offsets[p] + threadIdx.x);  // by reference: no private copy
 }
 
 __global__ __launch_bounds__(WG) void k_cell_close_batched(const Problem* probs, const long long* offsets,
                                                            int nprob, long long total) {
-    long long g = (long long)blockIdx.x * WG + threadIdx.x;
-    if (g >= total) return;
-    int p = find_problem(offsets, nprob, g);
-    cell_close_one(probs[p], g - offsets[p]);
+    const long long g0 = (long long)blockIdx.x * WG;
+    if (g0 >= total) return;
+    const int p = __builtin_amdgcn_readfirstlane(find_problem(offsets, nprob, g0));
+    cell_close_one(probs[p], g0 - offsets[p] + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -257,8 +257,9 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
         }
         face_off[j] = ft;
         cell_off[j] = ct;
-        ft += c->r.NE * c->r.D;
-        ct += c->r.N;
+        // each problem's closure threads start on a workgroup boundary
+        ft += (c->r.NE * c->r.D + 255) / 256 * 256;
+        ct += (c->r.N + 255) / 256 * 256;
     }
     b->face_total = ft;
     b->cell_total = ct;
