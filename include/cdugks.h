@@ -151,9 +151,10 @@ typedef struct {
                                moments gain (h/2) rho a and (h/2) rho u.a (eqs.
                                rhoubar, rhoEbar) and the W update the source
                                integrals dt (0, rho a, rho u.a) at t_n.  Needs the
-                               paper's reconstruction and the default face tile;
-                               single problems only (batches and the server
-                               refuse it with CDUGKS_ERR_INVALID). */
+                               paper's reconstruction and the default face tile
+                               (in batches, the batched tile of the storage form);
+                               batches, the server and the autotuner take such
+                               problems in classes of their own. */
 } cdugks_params;
 
 typedef struct cdugks_ctx cdugks_ctx;
@@ -281,9 +282,9 @@ void cdugks_server_destroy(cdugks_server* srv);
 
 /* ---------------- autotuner ----------------------------------------------
  * Times candidate launch shapes for the class of this problem (dimension,
- * storage, reconstruction, velocity count, cell-count bucket): the face-sum
- * tile shape (cdugks_params.face_tile's list, the shapes usable for the
- * problem), the velocity split of the update kernel and the persistent grid
+ * storage, reconstruction, acceleration or none, velocity count, cell-count
+ * bucket): the face-sum tile shape (cdugks_params.face_tile's list, the
+ * shapes usable for the problem), the velocity split of the update kernel and the persistent grid
  * size of batched launches.  The fastest is kept in a process-wide table, and
  * written as text to the file named by $CDUGKS_TUNE_CACHE when that is set
  * (read back at first use); contexts created afterwards with face_tile = 0 use

@@ -111,7 +111,7 @@ int face_sum_blocks_per_cu_d1(int storage, int tile);
 int face_sum_blocks_per_cu_d2(int storage, int tile);
 int face_sum_blocks_per_cu_d3(int storage, int tile);
 // Resident workgroups per CU of the batched face-sum kernel of a class.
-int batched_face_blocks_per_cu(int maxd, int storage);
+int batched_face_blocks_per_cu(int maxd, int storage, bool accel);
 hipError_t launch_face_close(const Problem& P, hipStream_t s);
 hipError_t launch_cell_close(const Problem& P, hipStream_t s);
 hipError_t launch_update(const Problem& P, hipStream_t s);
@@ -121,19 +121,19 @@ hipError_t launch_moments(const Problem& P, const double* W, double* rho, double
 hipError_t launch_to_f64(const Problem& P, const void* src, int row0, int nrows, double* dst, hipStream_t s);
 
 // Batched: one launch per phase across problems of one class (storage,
-// whether they have Dirichlet sides, and the reconstruction option, which
-// select the face-sum variant).  The
+// whether they have Dirichlet sides, the reconstruction option and whether
+// they have an external acceleration, which select the kernel variants).  The
 // tile-kernel launches are persistent (grid = resident slots; workgroups take
 // items from the device counter `queue`, which must be 0 at launch, and reset
 // the counter `other` of the other kernel of the pair); maxd is the largest
 // dimension in the class.  The per-face and per-cell closures take
 // per-problem prefix offsets (in threads).
 hipError_t launch_face_sums_batched(const Problem* probs, const WorkItem* items, int nitems, int grid,
-                                    int maxd, int storage, bool dirichlet, bool single_slope, int* queue,
-                                    int* other, hipStream_t s);
+                                    int maxd, int storage, bool dirichlet, bool single_slope, bool accel,
+                                    int* queue, int* other, hipStream_t s);
 hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, int nitems, int grid, int maxd,
-                                 int storage, int* queue, int* other, hipStream_t s);
-int batched_blocks_per_cu(int maxd, int storage, bool update);
+                                 int storage, bool accel, int* queue, int* other, hipStream_t s);
+int batched_blocks_per_cu(int maxd, int storage, bool accel, bool update);
 hipError_t launch_face_close_batched(const Problem* probs, const long long* offsets, int nprob,
                                      long long total, hipStream_t s);
 hipError_t launch_cell_close_batched(const Problem* probs, const long long* offsets, int nprob,

@@ -116,7 +116,8 @@ __global__ __launch_bounds__(WG, 2) void k_update(Problem P) {
     UpdateKernel<D, ST, ACC, ROWS>::run(P, (long long)blk * WG + threadIdx.x, slice, P.nslices_upd);
 }
 
-template <typename ST, int MAXD>
+// ACC: the class's problems have an external acceleration
+template <typename ST, int MAXD, bool ACC>
 __global__ __launch_bounds__(WG) void k_update_batched(const Problem* probs, const WorkItem* items, int nitems,
                                                        int* queue, int* other) {
     __shared__ int slot;
@@ -125,9 +126,9 @@ __global__ __launch_bounds__(WG) void k_update_batched(const Problem* probs, con
         const WorkItem it = load_uniform(items + w);
         const Problem P = load_uniform(probs + it.prob);
         const long long c = (long long)it.tile * WG + threadIdx.x;
-        if (P.D == 1) UpdateKernel<1, ST>::run(P, c, it.slice, it.nslices);
-        else if (MAXD >= 2 && P.D == 2) UpdateKernel<MAXD >= 2 ? 2 : 1, ST>::run(P, c, it.slice, it.nslices);
-        else if (MAXD >= 3) UpdateKernel<MAXD >= 3 ? 3 : 1, ST>::run(P, c, it.slice, it.nslices);
+        if (P.D == 1) UpdateKernel<1, ST, ACC>::run(P, c, it.slice, it.nslices);
+        else if (MAXD >= 2 && P.D == 2) UpdateKernel<MAXD >= 2 ? 2 : 1, ST, ACC>::run(P, c, it.slice, it.nslices);
+        else if (MAXD >= 3) UpdateKernel<MAXD >= 3 ? 3 : 1, ST, ACC>::run(P, c, it.slice, it.nslices);
     }
 }
 
@@ -331,23 +332,37 @@ hipError_t launch_to_f64(const Problem& P, const void* src, int row0, int nrows,
     } while (0)
 
 hipError_t launch_update_batched(const Problem* probs, const WorkItem* items, int nitems, int grid, int maxd,
-                                 int storage, int* queue, int* other, hipStream_t s) {
+                                 int storage, bool accel, int* queue, int* other, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-#define CDG_L(TT, MD)                                                                                    \
-    hipLaunchKernelGGL((k_update_batched<TT, MD>), dim3(grid), dim3(WG), 0, s, probs, items, nitems, queue, \
+    if (accel) {
+#define CDG_L(TT, MD)                                                                                          \
+    hipLaunchKernelGGL((k_update_batched<TT, MD, true>), dim3(grid), dim3(WG), 0, s, probs, items, nitems, queue, \
                        other)
-    CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
+        CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
 #undef CDG_L
+    } else {
+#define CDG_L(TT, MD)                                                                                           \
+    hipLaunchKernelGGL((k_update_batched<TT, MD, false>), dim3(grid), dim3(WG), 0, s, probs, items, nitems, queue, \
+                       other)
+        CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
+#undef CDG_L
+    }
     return hipGetLastError();
 }
 
-int batched_blocks_per_cu(int maxd, int storage, bool update) {
-    if (!update) return batched_face_blocks_per_cu(maxd, storage);
+int batched_blocks_per_cu(int maxd, int storage, bool accel, bool update) {
+    if (!update) return batched_face_blocks_per_cu(maxd, storage, accel);
     int n = 0;
     hipError_t e = hipSuccess;
-#define CDG_L(TT, MD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_update_batched<TT, MD>), WG, 0)
-    CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
+    if (accel) {
+#define CDG_L(TT, MD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_update_batched<TT, MD, true>), WG, 0)
+        CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
 #undef CDG_L
+    } else {
+#define CDG_L(TT, MD) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (k_update_batched<TT, MD, false>), WG, 0)
+        CDG_DISPATCH_MAXD(storage, maxd, CDG_L);
+#undef CDG_L
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return 0;

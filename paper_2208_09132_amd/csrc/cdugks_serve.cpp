@@ -2,8 +2,9 @@
 // the launch-shape autotuner.
 //
 // Batched: all problems of a batch advance together.  Per step there is one
-// persistent launch per class (storage precision, and whether the problems
-// have Dirichlet sides) for the face sums and for the update,
+// persistent launch per class (storage precision, whether the problems have
+// Dirichlet sides, the reconstruction option, and whether they have an
+// external acceleration) for the face sums and for the update,
 // and one launch each for the per-face and per-cell closures over all
 // problems.  Step sequences are captured as HIP graphs of chunk_steps steps.
 // Every kernel computes each (problem, tile, velocity slice) item exactly as
@@ -38,6 +39,7 @@ struct StorageClass {
     int storage = 0;
     bool dirichlet = false;  // members have Dirichlet sides (face-sum variant)
     bool single_slope = false;  // members use the single-slope reconstruction
+    bool accel = false;  // members have an external acceleration (kernel variants)
     int maxd = 1;
     WorkItem* items_fs = nullptr;  // device
     int n_fs = 0, grid_fs = 0;
@@ -79,7 +81,7 @@ std::string class_key(const Resolved& r) {
     long long nb = 1;
     while (nb < r.N) nb <<= 1;  // cell-count bucket: next power of two
     char buf[128];
-    snprintf(buf, sizeof buf, "d%d_s%d_r%d_v%lld_n%lld", r.D, r.storage, r.recon, r.V, nb);
+    snprintf(buf, sizeof buf, "d%d_s%d_r%d_a%d_v%lld_n%lld", r.D, r.storage, r.recon, r.has_accel ? 1 : 0, r.V, nb);
     return buf;
 }
 
@@ -150,16 +152,13 @@ hipError_t enqueue_batch_step(cdugks_batch* b, int phase) {
     const Problem* probs = b->d_probs[phase];
     for (auto& c : b->classes)
         if ((e = launch_face_sums_batched(probs, c.items_fs, c.n_fs, c.grid_fs, c.maxd, c.storage, c.dirichlet,
-                                            c.single_slope, c.queue,
-                                          c.queue + 1, b->stream)) !=
-            hipSuccess)
+                                          c.single_slope, c.accel, c.queue, c.queue + 1, b->stream)) != hipSuccess)
             return e;
     if ((e = launch_face_close_batched(probs, b->d_face_off, np, b->face_total, b->stream)) != hipSuccess) return e;
     if ((e = launch_cell_close_batched(probs, b->d_cell_off, np, b->cell_total, b->stream)) != hipSuccess) return e;
     for (auto& c : b->classes)
-        if ((e = launch_update_batched(probs, c.items_up, c.n_up, c.grid_up, c.maxd, c.storage, c.queue + 1,
-                                       c.queue, b->stream)) !=
-            hipSuccess)
+        if ((e = launch_update_batched(probs, c.items_up, c.n_up, c.grid_up, c.maxd, c.storage, c.accel,
+                                       c.queue + 1, c.queue, b->stream)) != hipSuccess)
             return e;
     return hipSuccess;
 }
@@ -220,8 +219,6 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
         if (!ctxs[j]) return fail(CDUGKS_ERR_INVALID, "null context in batch");
         if (ctxs[j]->in_batch) return fail(CDUGKS_ERR_BUSY, "context already belongs to a batch");
         if (ctxs[j]->sticky) return fail(ctxs[j]->sticky, "context is in an error state");
-        if (ctxs[j]->r.has_accel)
-            return fail(CDUGKS_ERR_INVALID, "contexts with an external acceleration run alone, not in batches");
         for (int k = 0; k < j; ++k)
             if (ctxs[k] == ctxs[j]) return fail(CDUGKS_ERR_INVALID, "context listed twice");
     }
@@ -263,14 +260,16 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
     }
     b->face_total = ft;
     b->cell_total = ct;
-    // work lists per class (index 2 storage + Dirichlet), sorted by estimated
-    // cost (largest first)
-    // 3 storage forms x (with, without Dirichlet sides) x 2 reconstructions
-    constexpr int NCLASS = 12;
+    // work lists per class, sorted by estimated cost (largest first):
+    // 3 storage forms x (with, without Dirichlet sides) x 2 reconstructions x
+    // (with, without an external acceleration)
+    constexpr int NCLASS = 24;
     std::vector<std::vector<WorkItem>> fs(NCLASS), up(NCLASS);
     std::vector<std::vector<double>> cfs(NCLASS), cup(NCLASS);
     int maxd[NCLASS] = {};
-    auto class_of = [](const Resolved& r) { return (2 * r.storage + (r.any_dirichlet ? 1 : 0)) * 2 + r.recon; };
+    auto class_of = [](const Resolved& r) {
+        return ((2 * r.storage + (r.any_dirichlet ? 1 : 0)) * 2 + r.recon) * 2 + (r.has_accel ? 1 : 0);
+    };
     for (int j = 0; j < count; ++j) {
         const Resolved& r = ctxs[j]->r;
         const int s = class_of(r);
@@ -348,17 +347,18 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
     for (int s = 0; s < NCLASS; ++s) {
         if (fs[s].empty()) continue;
         StorageClass sc;
-        sc.storage = s / 4;
-        sc.dirichlet = (s / 2) % 2 == 1;
-        sc.single_slope = s % 2 == 1;
+        sc.storage = s / 8;
+        sc.dirichlet = (s / 4) % 2 == 1;
+        sc.single_slope = (s / 2) % 2 == 1;
+        sc.accel = s % 2 == 1;
         sc.maxd = maxd[s];
         // persistent grids: resident slots (times the tuned factor of the
         // largest class member), never more than the work items
         int gf = 1;
         for (int j = 0; j < count; ++j)
             if (class_of(ctxs[j]->r) == s) gf = std::max(gf, tune_lookup(ctxs[j]->r).grid_factor);
-        int bfs = std::max(1, batched_blocks_per_cu(sc.maxd, sc.storage, false));
-        int bup = std::max(1, batched_blocks_per_cu(sc.maxd, sc.storage, true));
+        int bfs = std::max(1, batched_blocks_per_cu(sc.maxd, sc.storage, sc.accel, false));
+        int bup = std::max(1, batched_blocks_per_cu(sc.maxd, sc.storage, sc.accel, true));
         sc.items_fs = (WorkItem*)(b->dev + o_fs[s]);
         sc.n_fs = (int)fs[s].size();
         sc.grid_fs = (int)std::min<long long>(sc.n_fs, (long long)cus * bfs * gf);
@@ -638,8 +638,6 @@ int cdugks_submit(cdugks_server* s, const cdugks_space* space, const cdugks_velo
     if (rc) return rc;
     if (r.bytes > s->budget)
         return fail(CDUGKS_ERR_TOO_LARGE, "request needs %zu bytes, budget is %zu", r.bytes, s->budget);
-    if (r.has_accel)
-        return fail(CDUGKS_ERR_INVALID, "requests with an external acceleration are not served (run them alone)");
     for (long long c = 0; c < r.N; ++c)
         if (!(rho[c] > 0.0) || !(T[c] > 0.0) || !std::isfinite(rho[c]) || !std::isfinite(T[c]))
             return fail(CDUGKS_ERR_INVALID, "non-physical initial moments at cell %lld", c);
@@ -714,8 +712,6 @@ void cdugks_server_destroy(cdugks_server* s) {
 int cdugks_autotune(cdugks_ctx* c, int steps_per_trial) {
     if (!c || steps_per_trial <= 0) return fail(CDUGKS_ERR_INVALID, "bad argument");
     if (c->in_batch) return fail(CDUGKS_ERR_BUSY, "context belongs to a batch");
-    if (c->r.has_accel)
-        return fail(CDUGKS_ERR_INVALID, "autotuning times batched launches, which exclude an external acceleration");
     if (c->sticky) return fail(c->sticky, "context is in an error state");
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

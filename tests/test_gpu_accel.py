@@ -6,10 +6,12 @@ each velocity row's largest value.  Cases: 1-D free fall and the isothermal
 atmosphere with Dirichlet ends, 2-D random periodic states with several
 tiles and ragged edges, a 2-D Dirichlet side, 3-D FP64 and FP32 (the 3-D
 update stores the next quarter-step fields, which carry the acceleration's
-source).  Problems with an acceleration are refused by batches and the
-server."""
+source).  In batches, the server and after autotuning, problems with an
+acceleration (in classes of their own, beside problems without one) give
+bitwise their solo results; a batch member also matches the oracle."""
 import math
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -110,18 +112,103 @@ def test_uniform_free_fall_momentum_exact_on_gpu():
         assert abs(W[0, 1 + d] - want) <= 1e-13 * 1.3
 
 
-def test_batches_and_server_refuse_acceleration():
-    p = dict(wl.kelvin_helmholtz(n=16, nv=8), accel=[0.0, -1.0])
-    a, b = cd.Solver(p), cd.Solver(wl.kelvin_helmholtz(n=16, nv=8))
-    with pytest.raises(cd.CdugksError) as ei:
-        cd.Batch([a, b])
-    assert ei.value.code == cd.ERR_INVALID
-    a.close()
-    b.close()
-    srv = cd.Server(1 << 32, max_active=2, chunk_steps=2)
-    with pytest.raises(cd.CdugksError) as ei:
-        srv.submit(p, 4)
-    assert ei.value.code == cd.ERR_INVALID
+def _accel_mix():
+    """Problems with and without an acceleration: 1-D FP64 with Dirichlet
+    ends, 2-D FP64 and FP32 (the FP32 batched tile shape differs from the
+    solo one), 2-D BF16 tails, 3-D FP32 (stored quarter-step fields), and two
+    without an acceleration."""
+    a = wl.random_fourier(1, [130], [17], wl.SplitMix64(61), amp=0.2, Kn=1e-2)
+    a["accel"] = [0.7]
+    d = wl.sod(n=90, nv=20, boundary="dirichlet")
+    d["accel"] = [-0.4]
+    b = wl.random_fourier(2, [37, 21], [9, 10], wl.SplitMix64(62), amp=0.2, Kn=3e-2)
+    b["accel"] = [0.6, -0.9]
+    c = dict(wl.kelvin_helmholtz(n=40, nv=12), accel=[0.0, -0.5], storage="f32")
+    e = dict(c, storage="f32_bf16tail", accel=[0.2, -0.3])
+    f = wl.random_fourier(3, [17, 9, 11], [5, 6, 5], wl.SplitMix64(63), amp=0.2, Kn=3e-2)
+    f.update(bc=["outflow", "periodic", "periodic"], accel=[0.3, 0.8, -1.1], storage="f32")
+    g = wl.random_fourier(2, [24, 24], [8, 8], wl.SplitMix64(64), amp=0.2, Kn=1e-2)
+    h = dict(wl.random_fourier(1, [100], [12], wl.SplitMix64(65), amp=0.2, Kn=1e-1), storage="f32")
+    return [a, d, b, c, e, f, g, h]
+
+
+def _alone(prob, steps):
+    s = cd.Solver(prob)
+    s.step(steps)
+    m = s.moments()
+    gb = s.distributions()
+    s.close()
+    return m, gb
+
+
+def test_batched_acceleration_equals_alone_and_matches_oracle():
+    probs = _accel_mix()
+    steps = 9  # one 4-step graph chunk, twice, and a remainder
+    ref = [_alone(p, steps) for p in probs]
+    solvers = [cd.Solver(p) for p in probs]
+    bt = cd.Batch(solvers, chunk_steps=4)
+    bt.step(steps)
+    bt.close()
+    for k, (s, (m, gb)) in enumerate(zip(solvers, ref)):
+        got = s.moments()
+        for x, y in zip(got, m):
+            assert np.array_equal(x, y), f"problem {k} moments differ: {moment_errors(m, got)}"
+        for x, y in zip(s.distributions(), gb):
+            assert np.array_equal(x, y), f"problem {k} distributions differ"
+    _log(f"batched acceleration: {len(probs)} problems bitwise equal to their solo runs")
+    # a batch member against the oracle (the 2-D FP64 problem)
+    p, s = probs[2], solvers[2]
+    o = make_oracle(p, dt=dt_checked(p, s.dt))
+    assert o.step(steps) == 0
+    errs = moment_errors(o.moments(), s.moments())
+    _log(f"  batched 2-D FP64 member vs oracle: {errs}")
+    assert max(errs) <= 1e-12, errs
+    for s in solvers:
+        s.close()
+
+
+def test_served_acceleration_equals_alone():
+    probs = _accel_mix()
+    steps = [7, 5, 9, 6, 8, 4, 5, 7]
+    ref = [_alone(p, n)[0] for p, n in zip(probs, steps)]
+    need = [cd.cdugks_required_bytes(p) for p in probs]
+    srv = cd.Server(int(max(need) * 3.5), max_active=4, chunk_steps=3)  # forces queueing
+    tickets = [srv.submit(p, n) for p, n in zip(probs, steps)]
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets) and time.time() - t0 < 120:
+        for t in tickets:
+            if t not in done:
+                r = srv.poll(t)
+                if r is not None:
+                    done[t] = r
+        time.sleep(0.005)
     srv.close()
+    assert len(done) == len(tickets)
+    for k, (t, r) in enumerate(zip(tickets, ref)):
+        rho, u, T, tq, ts = done[t]
+        assert np.array_equal(rho, r[0]) and np.array_equal(u, r[1]) and np.array_equal(T, r[2]), k
+    _log(f"served acceleration: {len(probs)} requests bitwise equal to their solo runs")
+
+
+def test_autotuned_acceleration_keeps_results():
+    """The autotuner takes problems with an acceleration (its update and
+    batched-grid trials run batches of one): a context created after tuning
+    and the tuned context itself give bitwise the results of untuned runs."""
+    p = dict(wl.kelvin_helmholtz(n=40, nv=12), accel=[0.0, -0.5])
+    ref, _ = _alone(p, 6)  # before tuning
+    t = cd.Solver(p)
+    t.autotune(2)  # advances by its trial steps
+    n = t.info()[2]
+    t.step(6)
+    got_t = t.moments()
+    t.close()
+    _log(f"autotuned acceleration problem after {n} trial steps")
+    got, _ = _alone(p, 6)  # takes the tuned shapes of this class
+    for x, y in zip(got, ref):
+        assert np.array_equal(x, y)
+    ref_t, _ = _alone(p, n + 6)
+    for x, y in zip(got_t, ref_t):
+        assert np.array_equal(x, y)
     with pytest.raises(cd.CdugksError):  # acceleration with the single-slope option
         cd.Solver(dict(p, reconstruction="single_slope"))
