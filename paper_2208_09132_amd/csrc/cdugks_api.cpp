@@ -210,7 +210,7 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
         nt1 *= r.tiles1_def[d];
     }
     set_face_tile(r, 0);
-    const long long nt2 = (r.N + 255) / 256;  // update blocks of 256 cells
+    const long long nt2 = (r.N + WG - 1) / WG;  // update blocks of WG cells
     // Velocity slices: fill the chip's resident workgroup slots in whole
     // rounds.  The face-sum split fixes the summation order, so it depends only
     // on the problem and the device type, never on what else is running.

@@ -12,8 +12,6 @@
 
 namespace cdg {
 
-constexpr int WG = 256;
-
 __device__ __forceinline__ int map_coord(int x, int n, int bc) {
     if (bc == 0) {
         int r = x % n;

@@ -32,6 +32,9 @@ enum { PF_A = 0, PF_INV2RT, PF_CRT2, PF_IG, PF_IB, PF_EB, PF_HU2, PF_U0, NFP = P
 enum { VE_XI0 = 0, VE_W = 3, VE_HX2 = 4, VE_LAM0 = 5, VE_WXI0 = 8, VE_WXX = 11, VE_AX = 20, NVEL = 21 };
 
 constexpr int MAX_NSUM = 9;  // 2D+3 face sums for D = 3
+// threads per workgroup of the update and closure kernels (the per-problem
+// thread ranges of batched closures start on multiples of it)
+constexpr int WG = 256;
 
 // Whether the update kernel also stores the next step's quarter-step fields
 // phi_bar_plus (eq. phibarplus, from the new state and the new equilibrium it

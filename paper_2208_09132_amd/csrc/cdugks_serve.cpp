@@ -255,8 +255,8 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
         face_off[j] = ft;
         cell_off[j] = ct;
         // each problem's closure threads start on a workgroup boundary
-        ft += (c->r.NE * c->r.D + 255) / 256 * 256;
-        ct += (c->r.N + 255) / 256 * 256;
+        ft += (c->r.NE * c->r.D + WG - 1) / WG * WG;
+        ct += (c->r.N + WG - 1) / WG * WG;
     }
     b->face_total = ft;
     b->cell_total = ct;
@@ -286,7 +286,7 @@ int batch_build(cdugks_ctx* const* ctxs, int count, int chunk_steps, cdugks_batc
         // work enough to fill the device without the many short slices a
         // small problem uses alone, each of which loads the cell's and its
         // faces' coefficient sets again.
-        const int nb = (int)((r.N + 255) / 256);
+        const int nb = (int)((r.N + WG - 1) / WG);
         const int us = batch_update_slices(r);
         const double vpu = (double)r.V / us;
         for (int sl = 0; sl < us; ++sl)
