@@ -760,6 +760,92 @@ void oracle_set_state(oracle_state* s, const double* g, const double* b, const d
     if (W) memcpy(s->W, W, sizeof(double) * s->N * (s->D + 2));
 }
 
+/* ------------------------------------------------------------------ */
+/* velocity-grid refit (an adaptive velocity grid, Sec. 5)              */
+/* ------------------------------------------------------------------ */
+
+/* The state of src carried to the velocity grid of dst (same cells, gas and
+ * boundaries; dst's own velocity grid).  The paper names adaptive velocity
+ * grids only as an extension (Sec. 5).  Reading taken here, at a step
+ * boundary: the conserved variables W are carried unchanged (they are the
+ * scheme's state, Sec. 2.1); on the new grid each distribution is the
+ * equilibrium of the cell's W (eqs. geq, beq) plus the departure from
+ * equilibrium phi - phi_eq of the old grid, interpolated multilinearly in
+ * velocity between the old nodes and zero outside the old velocity box.
+ * Time and step count carry over.  Returns 0, -1 when the problems differ
+ * in their cells or dimension. */
+int oracle_regrid(const oracle_state* src, oracle_state* dst)
+{
+    const int D = src->D;
+    if (dst->D != D || dst->N != src->N) return -1;
+    for (int d = 0; d < D; ++d)
+        if (dst->p.n[d] != src->p.n[d]) return -1;
+    /* old axes: nodes per dimension */
+    double* ax[3] = {NULL, NULL, NULL};
+    long nvo[3] = {1, 1, 1};
+    for (int d = 0; d < D; ++d) {
+        nvo[d] = src->p.nv[d];
+        ax[d] = malloc(sizeof(double) * nvo[d]);
+        double* wtmp = malloc(sizeof(double) * nvo[d]);
+        if (!ax[d] || !wtmp) return -1;
+        oracle_velocity_axis(nvo[d], src->p.vmin[d], src->p.vmax[d], src->p.quad, ax[d], wtmp);
+        free(wtmp);
+    }
+    memcpy(dst->W, src->W, sizeof(double) * src->N * (D + 2));
+    for (long c = 0; c < src->N; ++c) {
+        prim_t q = primitives(src, src->W + c * (D + 2));
+        const double* go = src->g + c * src->V;
+        const double* bo = src->b + c * src->V;
+        for (long i = 0; i < dst->V; ++i) {
+            const double* xi = dst->xi + 3 * i;
+            double geq = g_equilibrium(dst, &q, xi);
+            double beq = b_equilibrium(dst, &q, xi, geq);
+            /* cell of the old grid holding xi, and the weights along each axis */
+            int inside = 1;
+            long m[3] = {0, 0, 0};
+            double t[3] = {0.0, 0.0, 0.0};
+            for (int d = 0; d < D; ++d) {
+                double lo = ax[d][0], hi = ax[d][nvo[d] - 1], h = ax[d][1] - ax[d][0];
+                if (xi[d] < lo || xi[d] > hi) {
+                    inside = 0;
+                    break;
+                }
+                long k = (long)floor((xi[d] - lo) / h);
+                if (k > nvo[d] - 2) k = nvo[d] - 2;
+                if (k < 0) k = 0;
+                m[d] = k;
+                t[d] = (xi[d] - ax[d][k]) / h;
+            }
+            double dg = 0.0, db = 0.0;
+            if (inside) {
+                /* the 2^D corners of the old cell */
+                for (int corner = 0; corner < (1 << D); ++corner) {
+                    double wgt = 1.0;
+                    long io = 0, stride = 1;
+                    double xo[3] = {0.0, 0.0, 0.0};
+                    for (int d = 0; d < D; ++d) {
+                        int up = (corner >> d) & 1;
+                        wgt *= up ? t[d] : 1.0 - t[d];
+                        io += (m[d] + up) * stride;
+                        stride *= nvo[d];
+                        xo[d] = ax[d][m[d] + up];
+                    }
+                    double ge = g_equilibrium(src, &q, xo);
+                    double be = b_equilibrium(src, &q, xo, ge);
+                    dg += wgt * (go[io] - ge);
+                    db += wgt * (bo[io] - be);
+                }
+            }
+            dst->g[c * dst->V + i] = geq + dg;
+            dst->b[c * dst->V + i] = beq + db;
+        }
+    }
+    for (int d = 0; d < D; ++d) free(ax[d]);
+    dst->t = src->t;
+    dst->steps = src->steps;
+    return 0;
+}
+
 double oracle_time(const oracle_state* s) { return s->t; }
 
 int oracle_num_threads(void)

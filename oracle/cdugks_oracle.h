@@ -76,6 +76,14 @@ void oracle_moments(const oracle_state* s, double* rho, double* u, double* T);
 void oracle_get_state(const oracle_state* s, double* g, double* b, double* W);
 void oracle_set_state(oracle_state* s, const double* g, const double* b, const double* W);
 
+/* Velocity-grid refit (an adaptive velocity grid; Sec. 5 names the idea):
+ * dst takes src's conserved variables unchanged and, on its own velocity
+ * grid, the equilibrium of each cell's W plus src's departure from
+ * equilibrium interpolated multilinearly in velocity (zero outside src's
+ * velocity box); time and step count carry over.  The problems must share
+ * dimension and cells.  Returns 0 or -1. */
+int oracle_regrid(const oracle_state* src, oracle_state* dst);
+
 /* Pieces exposed so tests can pin them individually. */
 double oracle_van_leer(double s1, double s2);
 void oracle_velocity_axis(long nv, double vmin, double vmax, int quad,

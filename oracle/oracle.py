@@ -89,6 +89,8 @@ def _load():
                                              ctypes.c_int, dp, dp]
         lib.oracle_equilibrium_moments.argtypes = [ctypes.c_void_p, ctypes.c_double, dp,
                                                    ctypes.c_double, dp]
+        lib.oracle_regrid.restype = ctypes.c_int
+        lib.oracle_regrid.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         lib.oracle_time.restype = ctypes.c_double
         lib.oracle_time.argtypes = [ctypes.c_void_p]
         lib.oracle_num_steps.restype = ctypes.c_long
@@ -234,6 +236,14 @@ class Oracle:
         out = np.zeros(self.D + 2)
         _load().oracle_equilibrium_moments(self._h, float(rho), _ptr(uu), float(T), _ptr(out))
         return out
+
+    def regrid_from(self, src: "Oracle") -> None:
+        """Take src's state on this problem's velocity grid (an adaptive
+        velocity grid, Sec. 5): W unchanged; phi = the equilibrium of W here
+        plus src's phi - phi_eq interpolated multilinearly in velocity (zero
+        outside src's velocity box)."""
+        if _load().oracle_regrid(src._h, self._h) != 0:
+            raise ValueError("oracle_regrid: the problems differ in cells or dimension")
 
     @property
     def time(self) -> float:

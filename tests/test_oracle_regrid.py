@@ -1,0 +1,142 @@
+"""Pins of the oracle's velocity-grid refit (an adaptive velocity grid; the
+paper names adaptive velocity grids as an extension in Sec. 5 and gives no
+algorithm).  Reading: at a step boundary W is carried unchanged; on the new
+grid phi = phi_eq(W) (eqs. geq, beq) + the old grid's phi - phi_eq
+interpolated multilinearly in velocity, zero outside the old velocity box.
+
+Each pin is fixed by that reading independently of the oracle's code, and
+aimed at a plausible mistake:
+
+  same grid                -> phi back to round-off, W bitwise (an index or
+                              weight mix-up moves values between nodes)
+  an equilibrium state     -> the discrete equilibrium of the new grid, as a
+                              fresh problem on that grid computes it (a wrong
+                              W -> primitives step, or a non-zero departure)
+  a departure linear in    -> reproduced exactly at every new node inside the
+  each velocity component     old box and zero outside it; with different
+  (plus a bilinear term)      coefficients per axis and per cell, so a
+                              transposed axis, a wrong corner weight or a
+                              wrong inside test fails
+  time and steps           -> carried
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2208_09132_amd import workloads as wl
+from tests.helpers import make_oracle, oracle_problem
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    orc.build(force=False)
+
+
+def _nodes(prob):
+    """Velocity nodes [V][D] of a problem, index i = m0 + nv0 (m1 + nv1 m2)."""
+    D = prob["dim"]
+    axes = [orc.velocity_axis(prob["nv"][d], prob["vmin"][d], prob["vmax"][d], prob.get("quad", "trapezoid"))[0]
+            for d in range(D)]
+    grids = np.meshgrid(*axes, indexing="ij")  # [m0][m1]...
+    return np.stack([g.transpose().reshape(-1) for g in grids], axis=1) if D > 1 else axes[0][:, None]
+
+
+def _equilibria(prob, W, nodes):
+    """g_eq, b_eq [N][V] of each cell's W at the given nodes (eqs. geq, beq)."""
+    D, R, gamma = prob["dim"], prob.get("R", 0.5), prob.get("gamma", 5.0 / 3.0)
+    K = (5.0 - 3.0 * gamma) / (gamma - 1.0)
+    rho = W[:, 0]
+    u = W[:, 1:1 + D] / rho[:, None]
+    E = W[:, D + 1] / rho
+    T = (gamma - 1.0) / R * (E - 0.5 * np.sum(u * u, axis=1))
+    RT = R * T
+    c2 = np.sum((nodes[None, :, :] - u[:, None, :]) ** 2, axis=2)
+    g = rho[:, None] * (2 * np.pi * RT[:, None]) ** (-0.5 * D) * np.exp(-c2 / (2 * RT[:, None]))
+    b = 0.5 * (np.sum(nodes ** 2, axis=1)[None, :] + (3.0 - D + K) * RT[:, None]) * g
+    return g, b
+
+
+def _problem(dim=2):
+    if dim == 1:
+        return wl.random_fourier(1, [23], [17], wl.SplitMix64(3), amp=0.2, Kn=1e-2)
+    return wl.random_fourier(2, [9, 7], [11, 8], wl.SplitMix64(4), amp=0.2, Kn=1e-2)
+
+
+def test_same_grid_gives_back_the_state():
+    for dim in (1, 2):
+        p = _problem(dim)
+        a = make_oracle(p)
+        assert a.step(3) == 0
+        b = orc.Oracle(oracle_problem(p))
+        b.regrid_from(a)
+        ga, ba, Wa = a.state()
+        gb, bb, Wb = b.state()
+        assert np.array_equal(Wa, Wb)
+        assert np.max(np.abs(gb - ga)) <= 1e-14 * np.max(np.abs(ga))
+        assert np.max(np.abs(bb - ba)) <= 1e-14 * np.max(np.abs(ba))
+        assert b.steps == 3 and b.time == a.time
+
+
+def test_equilibrium_state_goes_to_the_new_grids_discrete_equilibrium():
+    p = _problem(2)
+    a = make_oracle(p)
+    q = dict(p, nv=[15, 13], vmin=[-5.0, -4.0], vmax=[4.5, 6.0])
+    fresh = make_oracle(q, dt=oracle_problem(p)["dt"])
+    b = orc.Oracle(oracle_problem(q, dt=oracle_problem(p)["dt"]))
+    b.regrid_from(a)
+    gf, bf, Wf = fresh.state()
+    gb, bb, Wb = b.state()
+    assert np.array_equal(Wb, a.state()[2])
+    assert np.max(np.abs(gb - gf)) <= 1e-15 * np.max(gf)
+    assert np.max(np.abs(bb - bf)) <= 1e-15 * np.max(bf)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_linear_and_bilinear_departures_are_reproduced_inside_the_old_box(dim):
+    p = _problem(dim)
+    a = make_oracle(p)
+    g0, b0, W = a.state()
+    N = W.shape[0]
+    old = _nodes(p)
+    rng = np.random.default_rng(7)
+    cg = rng.uniform(-1e-3, 1e-3, size=(N, dim + 2))  # c0, c_d per axis, c_xy
+    cb = rng.uniform(-1e-3, 1e-3, size=(N, dim + 2))
+
+    def departure(coef, nodes):
+        v = coef[:, :1] + coef[:, 1:1 + dim] @ nodes.T
+        if dim == 2:
+            v = v + coef[:, 3:4] * (nodes[:, 0] * nodes[:, 1])[None, :]
+        return v
+
+    ge, be = _equilibria(p, W, old)
+    a.set_state(ge + departure(cg, old), be + departure(cb, old), W)
+    # the new box sticks out of the old one on some sides; nodes fall between
+    # the old ones
+    if dim == 1:
+        q = dict(p, nv=[29], vmin=[p["vmin"][0] - 1.3], vmax=[p["vmax"][0] - 0.7])
+    else:
+        q = dict(p, nv=[19, 14], vmin=[p["vmin"][0] + 0.37, p["vmin"][1] - 1.1],
+                 vmax=[p["vmax"][0] + 0.9, p["vmax"][1] - 0.45])
+    b = orc.Oracle(oracle_problem(q, dt=oracle_problem(p)["dt"]))
+    b.regrid_from(a)
+    gn, bn, Wn = b.state()
+    assert np.array_equal(Wn, W)
+    new = _nodes(q)
+    inside = np.all((new >= np.array(p["vmin"][:dim]) - 1e-12) & (new <= np.array(p["vmax"][:dim]) + 1e-12),
+                    axis=1)
+    assert 0 < inside.sum() < len(new)
+    gq, bq = _equilibria(q, W, new)
+    want_g = gq + np.where(inside[None, :], departure(cg, new), 0.0)
+    want_b = bq + np.where(inside[None, :], departure(cb, new), 0.0)
+    assert np.max(np.abs(gn - want_g)) <= 1e-13 * np.max(np.abs(want_g))
+    assert np.max(np.abs(bn - want_b)) <= 1e-13 * np.max(np.abs(want_b))
+
+
+def test_regrid_refuses_other_cells():
+    p = _problem(2)
+    a = make_oracle(p)
+    q = dict(p, n=[9, 8])
+    q["rho"] = np.ones(72)
+    b = orc.Oracle(oracle_problem(q, dt=oracle_problem(p)["dt"]))
+    with pytest.raises(ValueError):
+        b.regrid_from(a)
