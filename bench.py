@@ -316,6 +316,36 @@ def shear3d_leg(steps: int, warmup: int):
             "roofline": roofline_block("shear3d", "f32", N, V, ph, ups)}
 
 
+def refit_leg(steps: int = 20, nv_to: int = 32):
+    """Velocity-grid refit (cdugks_regrid, an adaptive velocity grid) of the
+    KH state after a few steps, from 28^2 to nv_to^2 velocities on the same
+    box, FP64: wall time of the call (a new context: allocation, set-up,
+    the carried W and the refit kernels) and its algorithmic bytes (old g, b
+    read once, new g, b written once)."""
+    import torch
+    name, p = workload("kh", "f64")
+    s = _solver(p)
+    s.step(steps)
+    s.sync()
+    q = dict(p, nv=[nv_to, nv_to])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = s.regrid(q)
+    wall = time.perf_counter() - t0
+    N, Vo, Vn = s.N, s.V, r.V
+    r.close()
+    s.close()
+    torch.cuda.empty_cache()
+    return {"workload": f"{name} -> {nv_to}x{nv_to} velocities", "storage": "f64", "cells": N,
+            "velocities_from": Vo, "velocities_to": Vn, "wall_ms": 1e3 * wall,
+            "algorithmic_bytes": 16 * N * (Vo + Vn)}
+
+
+def _solver(prob):
+    from paper_2208_09132_amd import cdugks as cd
+    return cd.Solver(prob, use_torch=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,6 +362,8 @@ def main():
     ap.add_argument("--shear3d-steps", type=int, default=10,
                     help="timed steps of the 3-D shear leg (FP32, 64^3 x 16^3); 0 skips it")
     ap.add_argument("--shear3d-warmup", type=int, default=5)
+    ap.add_argument("--no-refit", dest="refit", action="store_false",
+                    help="skip the velocity-grid refit leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run the library's FP64 distribution copy (for counter calibration)")
     args = ap.parse_args()
@@ -411,6 +443,8 @@ def main():
         out["served"] = served_run(args.served_requests)
     if args.config != "shear3d" and args.shear3d_steps > 0:
         out["shear3d_fp32"] = shear3d_leg(args.shear3d_steps, args.shear3d_warmup)
+    if args.config == "kh" and args.refit:
+        out["refit"] = refit_leg()
     out["copy_ceiling_GBps"] = copy_ceiling()
     out["roofline"]["frac_of_copy_ceiling"] = achieved / out["copy_ceiling_GBps"]
     if not args.no_cpu:

@@ -216,6 +216,24 @@ int cdugks_distributions(cdugks_ctx* ctx, double* g, double* b);
 #define CDUGKS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
 int cdugks_distributions_noalloc(cdugks_ctx* ctx, double* g, double* b);
 
+/* Velocity-grid refit: an adaptive velocity grid at a step boundary.  The
+ * paper names adaptive velocity grids as an extension (Sec. 5) without an
+ * algorithm; this is the reading taken.  Creates a new context (space and
+ * params as for cdugks_init; same cells, dimension and storage form as src,
+ * else CDUGKS_ERR_INVALID) on the velocity grid vel.  Its conserved
+ * variables W are src's, bitwise (the scheme's state, Sec. 2.1); each
+ * distribution is the equilibrium of the cell's W at the new node (eqs. geq,
+ * beq) plus src's departure from equilibrium phi - phi_eq interpolated
+ * multilinearly between src's nodes, zero outside src's velocity box.  The
+ * new context has its own time step (the CFL bound of its grid unless
+ * params->dt is set) and starts at src's simulated time and step count.
+ * src is read, not changed; it must not belong to a batch and must live on
+ * the current device.  hip_stream, arena and arena_bytes as for cdugks_init.
+ * Waits for src's stream and for the refit. */
+int cdugks_regrid(cdugks_ctx* src, const cdugks_space* space, const cdugks_velocity* vel,
+                  const cdugks_params* params, void* hip_stream, void* arena, size_t arena_bytes,
+                  cdugks_ctx** out);
+
 /* Storage of the context's distributions: the number of velocity rows held
  * in BF16 (0 unless CDUGKS_STORE_F32_BF16TAIL) and the bytes of one state
  * array (g or b) as laid out.  Either pointer may be NULL. */

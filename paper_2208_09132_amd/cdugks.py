@@ -80,6 +80,8 @@ def load_library():
         "cdugks_init": (ctypes.c_int, [ctypes.POINTER(cdugks_space), ctypes.POINTER(cdugks_velocity),
                                        ctypes.POINTER(cdugks_params), _DP, _DP, _DP, vp, vp, sz,
                                        ctypes.POINTER(vp)]),
+        "cdugks_regrid": (ctypes.c_int, [vp, ctypes.POINTER(cdugks_space), ctypes.POINTER(cdugks_velocity),
+                                         ctypes.POINTER(cdugks_params), vp, vp, sz, ctypes.POINTER(vp)]),
         "cdugks_step": (ctypes.c_int, [vp, i64]),
         "cdugks_sync": (ctypes.c_int, [vp]),
         "cdugks_moments": (ctypes.c_int, [vp, _DP, _DP, _DP, ctypes.c_int]),
@@ -298,6 +300,22 @@ class Solver:
         n = ctypes.c_int64()
         check(load_library().cdugks_info(self.ctx, ctypes.byref(dt), ctypes.byref(t), ctypes.byref(n)))
         return dt.value, t.value, n.value
+
+    def regrid(self, prob: dict) -> "Solver":
+        """A new solver for ``prob`` (this problem's cells, gas and storage
+        form on another velocity grid) holding this solver's state carried to
+        that grid by cdugks_regrid; this solver is unchanged."""
+        sp, ve, pa = describe(prob)
+        h = ctypes.c_void_p()
+        check(load_library().cdugks_regrid(self.ctx, ctypes.byref(sp), ctypes.byref(ve), ctypes.byref(pa), None,
+                                           None, 0, ctypes.byref(h)))
+        s = Solver.__new__(Solver)
+        s.prob = prob
+        s.D, s.N, _, _, _ = _fields(prob)
+        s.V = int(np.prod([prob["nv"][d] for d in range(s.D)]))
+        s._arena, s._stream, s._batch = None, None, None
+        s.ctx = h
+        return s
 
     def launch_info(self):
         """(face-sum tile shape, 1-based; face-sum velocity slices; update

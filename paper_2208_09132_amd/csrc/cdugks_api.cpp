@@ -177,6 +177,7 @@ int resolve(const cdugks_space* sp, const cdugks_velocity* ve, const cdugks_para
             rho_ref = s / (double)r.N;
         }
         double T_ref = pa->T_ref > 0.0 ? pa->T_ref : 1.0;
+        r.rho_ref = rho_ref;
         // hard-sphere mean free path lambda = 16 mu / (5 rho sqrt(2 pi R T))
         r.mu_ref = 5.0 / 16.0 * pa->Kn * L * rho_ref * std::sqrt(2.0 * M_PI * pa->R * T_ref);
         r.T_ref = T_ref;
@@ -747,6 +748,63 @@ int cdugks_init(const cdugks_space* space, const cdugks_velocity* vel, const cdu
     return CDUGKS_OK;
 }
 
+int cdugks_regrid(cdugks_ctx* src, const cdugks_space* space, const cdugks_velocity* vel,
+                  const cdugks_params* params, void* hip_stream, void* arena, size_t arena_bytes,
+                  cdugks_ctx** out) {
+    if (!out) return fail(CDUGKS_ERR_INVALID, "null output pointer");
+    *out = nullptr;
+    if (!src || !space || !vel || !params) return fail(CDUGKS_ERR_INVALID, "null argument");
+    if (src->in_batch) return fail(CDUGKS_ERR_BUSY, "context belongs to a batch");
+    if (src->sticky) return fail(src->sticky, "context is in an error state");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != src->device) {
+        (void)hipGetLastError();
+        return fail(CDUGKS_ERR_INVALID, "the source context lives on another device than the current one");
+    }
+    const Resolved& ro = src->r;
+    bool same = space->dim == ro.D;
+    for (int d = 0; same && d < ro.D; ++d) same = space->n[d] == ro.n[d];
+    if (!same) return fail(CDUGKS_ERR_INVALID, "a refit keeps the cells and dimension of its source");
+    // a Knudsen number refers to the source's reference density, not to the
+    // density the problem has reached
+    cdugks_params pa = *params;
+    if (pa.relax_mode == CDUGKS_RELAX_KN && !(pa.rho_ref > 0.0)) pa.rho_ref = ro.rho_ref;
+    // the source's moments (waits for its stream) set up the new context; W
+    // itself is then carried bitwise
+    std::vector<double> rho(ro.N), u((size_t)ro.D * ro.N), T(ro.N);
+    int rc = cdugks_moments(src, rho.data(), u.data(), T.data(), 0);
+    if (rc) return rc;
+    cdugks_ctx* c = nullptr;
+    rc = cdugks_init(space, vel, &pa, rho.data(), u.data(), T.data(), hip_stream, arena, arena_bytes, &c);
+    if (rc) return rc;
+    const Resolved& rn = c->r;
+    if (rn.N != ro.N || rn.storage != ro.storage) {
+        cdugks_destroy(c);
+        return fail(CDUGKS_ERR_INVALID, "a refit keeps the cells, dimension and storage form of its source");
+    }
+    Problem Pn = c->P, Po = src->P;
+    set_pingpong(Pn, rn, c->base, 0);
+    set_pingpong(Po, ro, src->base, src->cur);
+    hipError_t e = hipMemcpyAsync(const_cast<double*>(Pn.W_in), Po.W_in, sizeof(double) * (ro.D + 2) * ro.N,
+                                  hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = launch_regrid(Pn, Po, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    int flag = 0;
+    if (e == hipSuccess) e = hipMemcpy(&flag, c->base + rn.off_err, sizeof flag, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        cdugks_destroy(c);
+        return hip_fail(e, "velocity-grid refit");
+    }
+    if (flag) {
+        cdugks_destroy(c);
+        return fail(CDUGKS_ERR_NONPHYSICAL, "non-physical state in the refit");
+    }
+    c->t0 = src->t0 + ro.dt * (double)(src->steps - src->steps0);
+    c->steps = c->steps0 = src->steps;
+    *out = c;
+    return CDUGKS_OK;
+}
+
 int cdugks_storage_info(cdugks_ctx* c, int64_t* bf16_rows, size_t* state_array_bytes) {
     if (!c) return fail(CDUGKS_ERR_INVALID, "null context");
     if (bf16_rows) *bf16_rows = c->bf16_rows;
@@ -906,7 +964,7 @@ int cdugks_launch_info(cdugks_ctx* c, int* face_tile, int* face_slices, int* upd
 int cdugks_info(cdugks_ctx* c, double* dt, double* t, int64_t* steps) {
     if (!c) return fail(CDUGKS_ERR_INVALID, "null context");
     if (dt) *dt = c->r.dt;
-    if (t) *t = c->r.dt * (double)c->steps;
+    if (t) *t = c->t0 + c->r.dt * (double)(c->steps - c->steps0);
     if (steps) *steps = c->steps;
     return CDUGKS_OK;
 }

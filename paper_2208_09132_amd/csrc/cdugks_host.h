@@ -26,6 +26,7 @@ struct Resolved {
     int nslices, nslices_upd;
     int relax;
     double dt, gamma, Pr, R, omega, K, c_int, mu_ref, T_ref, tau_inv;
+    double rho_ref;     // reference density of a Knudsen-number relaxation (0 otherwise)
     // byte offsets inside the problem's device block
     size_t off_g[2], off_b[2], off_W[2], off_P[2];
     size_t off_q[2], off_dir, off_FV, off_FS, off_FP, off_G, off_vel, off_axis, off_err, off_scratch;
@@ -75,6 +76,8 @@ struct cdugks_ctx {
     bool own_memory = false;
     int cur = 0;          // buffer parity holding the current state
     int64_t steps = 0;
+    double t0 = 0.0;      // simulated time at steps0 (a refit context starts at its source's)
+    int64_t steps0 = 0;
     int sticky = 0;
     bool in_batch = false;
     long long bf16_rows = 0;  // BF16-tail form: velocity rows held in BF16

@@ -115,6 +115,9 @@ int face_sum_blocks_per_cu_d2(int storage, int tile);
 int face_sum_blocks_per_cu_d3(int storage, int tile);
 // Resident workgroups per CU of the batched face-sum kernel of a class.
 int batched_face_blocks_per_cu(int maxd, int storage, bool accel);
+// Velocity-grid refit: Pn (holding the carried W) takes Po's distributions
+// on its own velocity grid; same cells and storage form.
+hipError_t launch_regrid(const Problem& Pn, const Problem& Po, hipStream_t s);
 hipError_t launch_face_close(const Problem& P, hipStream_t s);
 hipError_t launch_cell_close(const Problem& P, hipStream_t s);
 hipError_t launch_update(const Problem& P, hipStream_t s);

@@ -107,6 +107,90 @@ __global__ __launch_bounds__(256) void k_init_quarter(Problem P) {
 
 
 
+// ---------------------------------------------------------------------------
+// Velocity-grid refit (an adaptive velocity grid; Sec. 5 names the idea).
+// The new problem Pn already holds the carried W.  k_cell_coefs sets its cell
+// coefficient sets from that W (with the new problem's dt); k_regrid writes,
+// per (new velocity, cell), phi_eq of the cell's W at the new node plus the
+// old problem's (Po) phi - phi_eq interpolated multilinearly between the old
+// nodes, zero outside the old velocity box.  Threads run velocity-major over
+// the cells, so the loads of one old node and the stores of one new node are
+// coalesced rows.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_cell_coefs(Problem P) {
+    const long long c = (long long)blockIdx.x * WG + threadIdx.x;
+    if (c >= P.N) return;
+    double Wv[5];
+    for (int k = 0; k < P.D + 2; ++k) Wv[k] = P.W_in[k * P.N + c];
+    const Prim q = primitives(P, Wv);
+    if (q.bad) raise_error(P.err);
+    write_cell_coefs(P, const_cast<double*>(P.P_in), P.N, c, q);
+}
+
+template <int D, typename ST>
+__global__ __launch_bounds__(WG) void k_regrid(Problem Pn, Problem Po) {
+    const long long idx = (long long)blockIdx.x * WG + threadIdx.x;
+    const long long N = Pn.N;
+    if (idx >= N * Pn.V) return;
+    const long long i = idx / N, c = idx - i * N;
+    const CellCoef k = load_coef(Pn.P_in, N, c);
+    const double* ve = Pn.vel + i * NVEL;
+    double xi[3] = {0.0, 0.0, 0.0};
+    double c2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        xi[d] = ve[VE_XI0 + d];
+        const double x = xi[d] - k.u[d];
+        c2 += x * x;
+    }
+    const double geq = k.A * exp(-c2 * k.inv2RT);
+    const double beq = (ve[VE_HX2] + k.cRT2) * geq;
+    // the old grid's cell holding xi, and the weights along each axis
+    bool inside = true;
+    int m[3] = {0, 0, 0}, off[3] = {0, 0, 0};
+    double t[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        off[d] = d == 0 ? 0 : off[d - 1] + Po.nv[d - 1];
+        const double* ax = Po.axis_xi + off[d];
+        const int nvo = Po.nv[d];
+        const double lo = ax[0], hi = ax[nvo - 1], h = ax[1] - ax[0];
+        if (!(xi[d] >= lo && xi[d] <= hi)) {
+            inside = false;
+        } else {
+            int kk = (int)floor((xi[d] - lo) / h);
+            kk = kk > nvo - 2 ? nvo - 2 : (kk < 0 ? 0 : kk);
+            m[d] = kk;
+            t[d] = (xi[d] - ax[kk]) / h;
+        }
+    }
+    double dg = 0.0, db = 0.0;
+    if (inside) {
+        for (int corner = 0; corner < (1 << D); ++corner) {
+            double wgt = 1.0, co2 = 0.0, xo2 = 0.0;
+            long long io = 0, stride = 1;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int up = (corner >> d) & 1;
+                wgt *= up ? t[d] : 1.0 - t[d];
+                const int mo = m[d] + up;
+                io += mo * stride;
+                stride *= Po.nv[d];
+                const double xo = Po.axis_xi[off[d] + mo];
+                const double x = xo - k.u[d];
+                co2 += x * x;
+                xo2 += xo * xo;
+            }
+            const double ge = k.A * exp(-co2 * k.inv2RT);
+            const double be = (0.5 * xo2 + k.cRT2) * ge;
+            dg += wgt * (state_ld<ST>(Po, Po.g_in, (int)io, c) - ge);
+            db += wgt * (state_ld<ST>(Po, Po.b_in, (int)io, c) - be);
+        }
+    }
+    state_st<ST, false>(Pn, const_cast<void*>(Pn.g_in), (int)i, c, geq + dg);
+    state_st<ST, false>(Pn, const_cast<void*>(Pn.b_in), (int)i, c, beq + db);
+}
+
 // update grid: blocks of 256 consecutive cells x velocity slices
 template <int D, typename ST, bool ACC = false, int ROWS = 0>
 __global__ __launch_bounds__(WG, 2) void k_update(Problem P) {
@@ -227,6 +311,20 @@ hipError_t launch_init(const Problem& P, const double* rho, const double* u, con
         const dim3 grid(blocks_for(P.N * P.V));
 #define CDG_L(D, ST) hipLaunchKernelGGL((k_init_quarter<D, ST>), grid, dim3(256), 0, s, P)
         CDG_DISPATCH(P.storage, P.D, CDG_L);
+#undef CDG_L
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_regrid(const Problem& Pn, const Problem& Po, hipStream_t s) {
+    hipLaunchKernelGGL(k_cell_coefs, dim3(blocks_for(Pn.N)), dim3(WG), 0, s, Pn);
+    const dim3 grid(blocks_for(Pn.N * Pn.V));
+#define CDG_L(D, ST) hipLaunchKernelGGL((k_regrid<D, ST>), grid, dim3(WG), 0, s, Pn, Po)
+    CDG_DISPATCH(Pn.storage, Pn.D, CDG_L);
+#undef CDG_L
+    if (quarter_stored(Pn.D)) {
+#define CDG_L(D, ST) hipLaunchKernelGGL((k_init_quarter<D, ST>), grid, dim3(256), 0, s, Pn)
+        CDG_DISPATCH(Pn.storage, Pn.D, CDG_L);
 #undef CDG_L
     }
     return hipGetLastError();

@@ -1,0 +1,129 @@
+"""GPU parity of the velocity-grid refit (cdugks_regrid; an adaptive velocity
+grid, named in Sec. 5 of the paper as an extension) against the oracle's
+refit on the same seeded inputs: W carried bitwise, g and b element by
+element (FP64 within 1e-12 of each velocity row's largest value), then both
+continue on the new grid with their own CFL step and their moments stay
+within 1e-12 (FP64) or 1e-5 (FP32, BF16 tails).  Cases: 2-D periodic with a
+new box sticking out of the old one on some sides, 1-D with Dirichlet ends
+onto a finer grid, 3-D in FP64 and FP32 (the quarter-step fields are
+recomputed for the new grid), 2-D BF16 tails; time and step count carried;
+other cells and another storage form refused."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2208_09132_amd import cdugks as cd
+from paper_2208_09132_amd import workloads as wl
+from tests.helpers import dt_checked, make_oracle, moment_errors, oracle_problem
+from oracle import oracle as orc
+from tests.test_gpu_distributions import row_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def refit_parity(p, q, before, after, tol, row_tol, floor=0.0, tol_abs=0.0):
+    """p stepped `before` steps, refit onto q's velocity grid, then `after`
+    more steps, on the GPU and in the oracle.  With floor > 0 (FP32 storage)
+    rows whose largest value is below floor times the field's largest are
+    held to tol_abs of the field's largest instead: their values leave FP32's
+    range (a 3-D tail row near 1e-64 is 0 in FP32).  The FP32 rows above the
+    floor are held to 1e-5 (the FP32 form's tolerance): a new node's
+    departure from equilibrium is interpolated from old nodes whose values,
+    on a coarse grid's steep tails, exceed the new node's by orders of
+    magnitude, so their storage rounding (6e-8 of their values per step) is a
+    larger fraction of the new row."""
+    _log(f"refit parity: dim={p['dim']} n={p['n']} nv {p['nv']} -> {q['nv']} storage={p.get('storage')} "
+         f"steps {before} + {after}")
+    s = cd.Solver(p)
+    o = make_oracle(p, dt=dt_checked(p, s.dt))
+    s.step(before)
+    assert o.step(before) == 0
+    r = s.regrid(q)
+    on = orc.Oracle(oracle_problem(q, dt=dt_checked(q, r.dt)))
+    on.regrid_from(o)
+    assert np.array_equal(r.conserved(), s.conserved())
+    dt_o, t_o, n_o = s.info()
+    dt_n, t_n, n_n = r.info()
+    assert n_n == n_o == before and t_n == t_o
+    g, b = r.distributions()
+    og, ob, _ = on.state()
+    if floor > 0.0:
+        (eg, ag), (eb, ab) = row_errors(og, g, floor), row_errors(ob, b, floor)
+        _log(f"  refit g, b per-row relative errors {eg:.2e}, {eb:.2e} (rows above {floor:g} of the largest); "
+             f"all rows {ag:.2e}, {ab:.2e} of the largest")
+        assert ag <= tol_abs and ab <= tol_abs
+    else:
+        eg, eb = row_errors(og, g), row_errors(ob, b)
+        _log(f"  refit g, b per-row relative errors {eg:.2e}, {eb:.2e}")
+    assert eg <= row_tol and eb <= row_tol
+    r.step(after)
+    assert on.step(after) == 0
+    errs = moment_errors(on.moments(), r.moments(), p.get("gamma", 5.0 / 3.0), p.get("R", 0.5))
+    _log(f"  after {after} more steps: errors rho/u/T = {errs}")
+    assert max(errs) <= tol, errs
+    # the source is unchanged by the refit
+    s.step(1)
+    assert o.step(1) == 0
+    assert max(moment_errors(o.moments(), s.moments(), p.get("gamma", 5.0 / 3.0), p.get("R", 0.5))) <= tol
+    s.close()
+    r.close()
+
+
+def test_refit_2d_periodic_box_partly_outside():
+    p = wl.random_fourier(2, [37, 21], [9, 10], wl.SplitMix64(71), amp=0.2, Kn=3e-2)
+    q = dict(p, nv=[13, 11], vmin=[p["vmin"][0] + 0.37, p["vmin"][1] - 1.1],
+             vmax=[p["vmax"][0] + 0.9, p["vmax"][1] - 0.45])
+    refit_parity(p, q, 5, 6, 1e-12, 1e-12)
+
+
+def test_refit_1d_dirichlet_onto_a_finer_grid():
+    p = wl.sod(n=128, nv=24, boundary="dirichlet")
+    q = dict(p, nv=[61])
+    refit_parity(p, q, 20, 20, 1e-12, 1e-12)
+
+
+def test_refit_3d_fp64_and_fp32():
+    p = wl.random_fourier(3, [17, 9, 11], [5, 6, 5], wl.SplitMix64(72), amp=0.2, Kn=3e-2)
+    p["bc"] = ["outflow", "periodic", "periodic"]
+    q = dict(p, nv=[7, 6, 8], vmin=[-7.0, -5.5, -6.0], vmax=[6.5, 6.0, 7.0])
+    refit_parity(p, q, 3, 3, 1e-12, 1e-12)
+    p32, q32 = dict(p, storage="f32"), dict(q, storage="f32")
+    refit_parity(p32, q32, 3, 3, 1e-5, 1e-5, floor=1e-10, tol_abs=1e-6)
+
+
+def test_refit_2d_bf16_tails():
+    p = dict(wl.kelvin_helmholtz(n=40, nv=12), storage="f32_bf16tail")
+    q = dict(p, nv=[16, 14])
+    s = cd.Solver(p)
+    o = make_oracle(p, dt=dt_checked(p, s.dt))
+    s.step(4)
+    assert o.step(4) == 0
+    r = s.regrid(q)
+    on = orc.Oracle(oracle_problem(q, dt=dt_checked(q, r.dt)))
+    on.regrid_from(o)
+    r.step(4)
+    assert on.step(4) == 0
+    errs = moment_errors(on.moments(), r.moments())
+    _log(f"refit BF16 tails: errors rho/u/T = {errs}")
+    assert max(errs) <= 1e-5, errs
+    s.close()
+    r.close()
+
+
+def test_refit_refuses_other_cells_and_storage():
+    p = wl.random_fourier(2, [12, 10], [6, 6], wl.SplitMix64(73), amp=0.2, Kn=1e-2)
+    s = cd.Solver(p)
+    q = dict(p, n=[12, 11], rho=np.ones(132), u=np.zeros((2, 132)), T=np.ones(132))
+    with pytest.raises(cd.CdugksError) as ei:
+        s.regrid(q)
+    assert ei.value.code == cd.ERR_INVALID
+    with pytest.raises(cd.CdugksError) as ei:
+        s.regrid(dict(p, storage="f32"))
+    assert ei.value.code == cd.ERR_INVALID
+    s.close()
