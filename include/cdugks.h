@@ -234,6 +234,23 @@ int cdugks_regrid(cdugks_ctx* src, const cdugks_space* space, const cdugks_veloc
                   const cdugks_params* params, void* hip_stream, void* arena, size_t arena_bytes,
                   cdugks_ctx** out);
 
+/* Velocity grid fitted to a state (host only, no device work): the paper's
+ * criterion for its fixed grid (Sec. 5: fine enough to resolve the mass and
+ * wide enough to hold it, to an integration error tol) applied to the
+ * moments rho[N], u[dim][N], T[N] (e.g. a context's current ones), for use
+ * with cdugks_regrid.  Per axis d the box is [min_c (u_d - k s_c),
+ * max_c (u_d + k s_c)] with s_c = sqrt(R T_c) and k = sqrt(2 ln(1/tol)) (the
+ * normal tail beyond k s is at most tol/2 on each side); the node spacing is
+ * at most pi sqrt(2) s_min / sqrt(ln(2/tol)) (the trapezoid rule's first
+ * aliasing error on a Gaussian of deviation s_min, 2 exp(-2 pi^2 s^2/h^2),
+ * is then at most tol); nv_d = ceil(width / spacing) + 1, rounded up to
+ * 4n + 1 for CDUGKS_QUAD_BOOLE.  Uses space->dim and n, params->R (0: 1/2).
+ * CDUGKS_ERR_INVALID for tol outside (0, 1), an unknown rule or
+ * non-physical moments. */
+int cdugks_fit_velocity(const cdugks_space* space, const cdugks_params* params, const double* rho,
+                        const double* u, const double* T, double tol, int quadrature,
+                        cdugks_velocity* out);
+
 /* Storage of the context's distributions: the number of velocity rows held
  * in BF16 (0 unless CDUGKS_STORE_F32_BF16TAIL) and the bytes of one state
  * array (g or b) as laid out.  Either pointer may be NULL. */

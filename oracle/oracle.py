@@ -133,6 +133,32 @@ def cfl_dt(cfl: float, dx_min: float, xi_max: float) -> float:
     return cfl * dx_min / (2.0 * xi_max)
 
 
+def fit_velocity(rho, u, T, R: float, tol: float, quad: str = "trapezoid"):
+    """Velocity grid fitted to moments rho[N], u[D][N], T[N] by the paper's
+    criterion for its fixed grid (Sec. 5: resolve the mass and hold all of
+    it, to an integration error tol), written out: per axis the box holds
+    u_d +- k s of every cell, s = sqrt(R T), k = sqrt(2 ln(1/tol)) (one-sided
+    normal tail at most exp(-k^2/2)/2 = tol/2); the spacing is at most
+    pi sqrt(2) s_min / sqrt(ln(2/tol)), where the trapezoid rule's first
+    aliasing error on a Gaussian, 2 exp(-2 pi^2 s^2/h^2), equals tol;
+    nv = ceil(width/spacing) + 1, rounded up to 4n + 1 for Boole.  Returns
+    (nv, vmin, vmax) lists."""
+    u = np.asarray(u, dtype=np.float64)
+    s = np.sqrt(R * np.asarray(T, dtype=np.float64))
+    k = math.sqrt(2.0 * math.log(1.0 / tol))
+    h = math.pi * float(s.min()) * math.sqrt(2.0) / math.sqrt(math.log(2.0 / tol))
+    nv, vmin, vmax = [], [], []
+    for d in range(u.shape[0]):
+        lo, hi = float(np.min(u[d] - k * s)), float(np.max(u[d] + k * s))
+        n = max(int(math.ceil((hi - lo) / h)) + 1, 2)
+        if quad == "boole":
+            n = (n - 1 + 3) // 4 * 4 + 1
+        nv.append(n)
+        vmin.append(lo)
+        vmax.append(hi)
+    return nv, vmin, vmax
+
+
 class Oracle:
     """One CDUGKS problem on the CPU.
 

@@ -17,8 +17,9 @@ UNITS = [("cdugks_kernels.hip", "cdugks_kernels", []),
          ("cdugks_face_sums.hip", "cdugks_face_sums_d3", ["-DCDG_FACE_DIM=3"]),
          ("cdugks_batched.hip", "cdugks_batched", []),
          ("cdugks_api.cpp", "cdugks_api", []),
-         ("cdugks_serve.cpp", "cdugks_serve", [])]
-JOBS = int(os.environ.get("CDUGKS_BUILD_JOBS", "7"))
+         ("cdugks_serve.cpp", "cdugks_serve", []),
+         ("cdugks_vgrid.cpp", "cdugks_vgrid", [])]
+JOBS = int(os.environ.get("CDUGKS_BUILD_JOBS", "8"))
 ARCH = os.environ.get("CDUGKS_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -82,6 +82,9 @@ def load_library():
                                        ctypes.POINTER(vp)]),
         "cdugks_regrid": (ctypes.c_int, [vp, ctypes.POINTER(cdugks_space), ctypes.POINTER(cdugks_velocity),
                                          ctypes.POINTER(cdugks_params), vp, vp, sz, ctypes.POINTER(vp)]),
+        "cdugks_fit_velocity": (ctypes.c_int, [ctypes.POINTER(cdugks_space), ctypes.POINTER(cdugks_params), _DP,
+                                               _DP, _DP, ctypes.c_double, ctypes.c_int,
+                                               ctypes.POINTER(cdugks_velocity)]),
         "cdugks_step": (ctypes.c_int, [vp, i64]),
         "cdugks_sync": (ctypes.c_int, [vp]),
         "cdugks_moments": (ctypes.c_int, [vp, _DP, _DP, _DP, ctypes.c_int]),
@@ -204,6 +207,21 @@ def cdugks_init(prob: dict, stream=None, arena=None, arena_bytes: int = 0):
     check(load_library().cdugks_init(ctypes.byref(sp), ctypes.byref(ve), ctypes.byref(pa), _ptr(rho), _ptr(u),
                                      _ptr(T), stream, arena, arena_bytes, ctypes.byref(h)))
     return h
+
+
+def fit_velocity(prob: dict, rho, u, T, tol: float, quad: str = "trapezoid") -> dict:
+    """cdugks_fit_velocity for prob's space and gas at the moments rho, u, T:
+    returns prob with nv, vmin, vmax and quad replaced by the fitted grid."""
+    sp, _, pa = describe(prob)
+    D = int(prob["dim"])
+    rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+    T = np.ascontiguousarray(T, dtype=np.float64).reshape(-1)
+    ve = cdugks_velocity()
+    check(load_library().cdugks_fit_velocity(ctypes.byref(sp), ctypes.byref(pa), _ptr(rho), _ptr(u), _ptr(T),
+                                             float(tol), 1 if quad == "boole" else 0, ctypes.byref(ve)))
+    return dict(prob, nv=[int(ve.nv[d]) for d in range(D)], vmin=[ve.vmin[d] for d in range(D)],
+                vmax=[ve.vmax[d] for d in range(D)], quad=quad)
 
 
 def cdugks_step(ctx, nsteps: int) -> None:

@@ -140,3 +140,68 @@ def test_regrid_refuses_other_cells():
     b = orc.Oracle(oracle_problem(q, dt=oracle_problem(p)["dt"]))
     with pytest.raises(ValueError):
         b.regrid_from(a)
+
+
+# ---------------------------------------------------------------------------
+# Velocity grid fitted to a state (the paper's criterion for its fixed grid,
+# Sec. 5): the library's host rule against the oracle's, and the property the
+# rule exists for.
+# ---------------------------------------------------------------------------
+
+def _fit_states():
+    rng = np.random.default_rng(11)
+    out = []
+    for D, N in ((1, 40), (2, 30), (3, 12)):
+        rho = rng.uniform(0.5, 2.0, N)
+        u = rng.uniform(-0.8, 0.8, (D, N))
+        T = rng.uniform(0.2, 1.5, N)
+        out.append((D, rho, u, T))
+    return out
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-10, 1e-13])
+def test_fitted_grid_holds_and_resolves_every_cells_maxwellian(tol):
+    """On the fitted grid the discrete moments of each cell's equilibrium
+    (mass, momentum, energy; eqs. geq, beq) match the exact ones within a few
+    tol (mass and energy relative to rho and rho E, momentum to rho sqrt(R T))."""
+    for D, rho, u, T in _fit_states():
+        nv, vmin, vmax = orc.fit_velocity(rho, u, T, 0.5, tol)
+        p = wl.random_fourier(D, [2] * D, nv, wl.SplitMix64(1), amp=0.0, Kn=1e-2)
+        p.update(vmin=vmin, vmax=vmax)
+        o = orc.Oracle(oracle_problem(p, dt=1e-3))
+        K = 0.0  # gamma 5/3
+        worst = 0.0
+        for c in range(len(rho)):
+            got = o.equilibrium_moments(rho[c], u[:, c], T[c])
+            RT = 0.5 * T[c]
+            E = rho[c] * (0.5 * np.sum(u[:, c] ** 2) + 0.5 * (3.0 + K) * RT)
+            worst = max(worst, abs(got[0] - rho[c]) / rho[c],
+                        float(np.max(np.abs(got[1:1 + D] - rho[c] * u[:, c]))) / (rho[c] * np.sqrt(RT)),
+                        abs(got[D + 1] - E) / E)
+        assert worst <= 10 * tol, (D, tol, nv, worst)
+
+
+def test_library_fit_equals_the_oracle_rule():
+    from paper_2208_09132_amd import cdugks as cd
+    for quad in ("trapezoid", "boole"):
+        for tol in (1e-6, 1e-12):
+            for D, rho, u, T in _fit_states():
+                p = wl.random_fourier(D, [len(rho)] + [1] * (D - 1), [4] * D, wl.SplitMix64(2), amp=0.0, Kn=1e-2)
+                got = cd.fit_velocity(p, rho, u, T, tol, quad)
+                nv, vmin, vmax = orc.fit_velocity(rho, u, T, 0.5, tol, quad)
+                assert got["nv"] == nv, (D, quad, tol)
+                assert np.allclose(got["vmin"], vmin, rtol=1e-15, atol=1e-15)
+                assert np.allclose(got["vmax"], vmax, rtol=1e-15, atol=1e-15)
+                if quad == "boole":
+                    assert all((n - 1) % 4 == 0 for n in nv)
+
+
+def test_library_fit_refuses_bad_input():
+    from paper_2208_09132_amd import cdugks as cd
+    D, rho, u, T = _fit_states()[0]
+    p = wl.random_fourier(1, [len(rho)], [4], wl.SplitMix64(2), amp=0.0, Kn=1e-2)
+    for tol in (0.0, 1.0, -1e-3):
+        with pytest.raises(cd.CdugksError):
+            cd.fit_velocity(p, rho, u, T, tol)
+    with pytest.raises(cd.CdugksError):
+        cd.fit_velocity(p, rho, u, np.where(np.arange(len(T)) == 3, -1.0, T), 1e-6)
