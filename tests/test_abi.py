@@ -135,6 +135,25 @@ def test_null_context_is_rejected():
     lib.cdugks_destroy(None)  # NULL-safe
 
 
+def test_refit_and_grid_fit_validate_their_arguments():
+    import ctypes
+    lib = cd.load_library()
+    p = wl.sod(n=16, nv=8)
+    sp, ve, pa = cd.describe(p)
+    out = ctypes.c_void_p()
+    # no source context / no output pointer
+    assert lib.cdugks_regrid(None, ctypes.byref(sp), ctypes.byref(ve), ctypes.byref(pa), None, None, 0,
+                             ctypes.byref(out)) == cd.ERR_INVALID
+    assert lib.cdugks_regrid(None, ctypes.byref(sp), ctypes.byref(ve), ctypes.byref(pa), None, None, 0,
+                             None) == cd.ERR_INVALID
+    # the grid fit is host arithmetic: a Boole grid has 4n + 1 nodes
+    q = cd.fit_velocity(p, p["rho"], p["u"], p["T"], 1e-9, quad="boole")
+    assert (q["nv"][0] - 1) % 4 == 0 and q["vmin"][0] < 0.0 < q["vmax"][0]
+    with pytest.raises(cd.CdugksError) as ei:
+        cd.fit_velocity(p, p["rho"], p["u"], p["T"], 2.0)
+    assert ei.value.code == cd.ERR_INVALID
+
+
 @pytest.mark.gpu
 def test_destroying_a_batched_context_is_refused():
     """cdugks_destroy of a context that belongs to a live batch leaves it
